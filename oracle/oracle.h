@@ -1,0 +1,75 @@
+/* oracle.h -- FP64 single-threaded CPU oracle of the hybrid-ocean hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or constant generator with the GPU library.
+ *
+ * Every value is computed in double precision, in plain loops, one thread.
+ * Integer decisions (counts, codes, fixed-point positions, bins) are made
+ * exactly as the method's fixed-point reading defines them.
+ *
+ * Canonical particle record (10 x int64), shared as a *format* with the GPU
+ * library's test hooks:
+ *   [0] patch  [1] bucket  [2] kind (0 boundary, 1 source)  [3] level
+ *   [4] code   [5] birth   [6] origin_x  [7] origin_y  (2^-20 m, anchor-relative)
+ *   [8] source (-1 for boundary)  [9] ring slot (0 for boundary)
+ */
+#ifndef HWO_ORACLE_H
+#define HWO_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_ocean orc_ocean;
+
+orc_ocean *orc_create(int32_t fft_n, double fft_L, double g, double dt, uint64_t seed);
+void orc_destroy(orc_ocean *o);
+const char *orc_error(const orc_ocean *o);
+
+int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, double spread_s,
+                     double wind_dir, int32_t n_buckets, double lambda_min, double lambda_max,
+                     double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode);
+int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, double dx,
+                  double eta, double band, int32_t follow);
+int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,
+                   double draft, int32_t ring_n, int32_t patch);
+int orc_set_bins(orc_ocean *o, const int32_t *bin_cells);
+int orc_step(orc_ocean *o, int32_t nsteps);
+int64_t orc_step_index(const orc_ocean *o);
+
+/* outputs at t_n = n*dt */
+int orc_background(orc_ocean *o, double *H);
+int orc_background_at(orc_ocean *o, double t, double *H);
+int orc_patch_maps(orc_ocean *o, int32_t patch, const double *H, double *raw, double *blended);
+int orc_counts(const orc_ocean *o, int32_t patch, int64_t *dst);
+int orc_tile_dims(const orc_ocean *o, int32_t patch, int32_t bucket, int64_t *dims);
+int orc_tiles(const orc_ocean *o, int32_t patch, int32_t bucket, int64_t *dst, int64_t n);
+int64_t orc_num_particles(const orc_ocean *o);
+int64_t orc_particles(const orc_ocean *o, int64_t *dst, int64_t n);
+int orc_window(const orc_ocean *o, int32_t patch, int64_t *w);
+
+/* tables and pins */
+double orc_jonswap(const orc_ocean *o, double w);
+double orc_dir(const orc_ocean *o, double w, double theta);
+double orc_spread(const orc_ocean *o, double w);
+int orc_spectrum_consts(const orc_ocean *o, double *out);
+int orc_bucket(const orc_ocean *o, int32_t i, double *out);
+int orc_patch_bucket(const orc_ocean *o, int32_t p, int32_t i, double *out);
+int orc_dir_table(const orc_ocean *o, int32_t i, int64_t *q, int64_t *cdf, int64_t *codes);
+int orc_velocity(const orc_ocean *o, int32_t i, int32_t code, int64_t *v);
+int orc_source_info(const orc_ocean *o, int32_t s, double *out);
+int64_t orc_inject_count(const orc_ocean *o, int32_t p, int32_t i, int32_t pair, int64_t n);
+void orc_philox4x64(const uint64_t *ctr, const uint64_t *key, uint64_t *out);
+void orc_fft_inverse(double *re, double *im, int32_t n);
+void orc_fft2_inverse(double *re, double *im, int32_t n);
+void orc_dft2_inverse(const double *re, const double *im, double *ore, double *oim, int32_t n);
+int orc_h0(const orc_ocean *o, double *re, double *im);
+int orc_set_h0(orc_ocean *o, const double *re, const double *im);
+int orc_splat(orc_ocean *o, int32_t patch, const int64_t *recs, int64_t n, double *raw);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

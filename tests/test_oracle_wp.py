@@ -1,0 +1,314 @@
+"""Pins of the oracle's wave-particle branch and blend (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+from paper_2511_02852_amd import scenes
+
+UNIT = 2 ** 20
+
+
+def pin_scene(nx=64, dx=0.25, lam=(1.0, 4.0), band=0.0):
+    """One bucket with lambda_i = sqrt(1 * 4) = 2 m, so r = 1 m = 4 cells."""
+    sp = scenes.Spectrum(U10=10.0, n_buckets=1, lambda_min=lam[0], lambda_max=lam[1], eta=4.0)
+    return scenes.Scene(name="pin", fft_n=64, fft_L=256.0, seed=3, steps=0, spectrum=sp,
+                        patches=[scenes.Patch(anchor_x=0.0, anchor_y=0.0, nx=nx, ny=nx, dx=dx,
+                                              blend_band=band)],
+                        bins=[8])
+
+
+def rec(x_u, y_u, code, bucket=0, birth=0, kind=0, level=0, src=-1, slot=0, patch=0):
+    return [patch, bucket, kind, level, code, birth, x_u, y_u, src, slot]
+
+
+# ---------------------------------------------------------------- splat
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_pair_lattice_sums_to_cosine(axis):
+    """Fig 1: particles at spacing lambda along their direction and r across
+    compose a wave.  With the raised cosine w (a partition of unity at spacing
+    r) and each particle a crest/trough pair r apart, the lattice sums to
+    exactly A cos(k (x - x0)), k = 2 pi / lambda."""
+    s = pin_scene()
+    o = oracle.Oracle(s)
+    r = o.bucket(0)["r"]
+    lam = o.bucket(0)["lam"]
+    A = o.patch_bucket(0, 0)["A"]
+    x0 = 3.3
+    recs = []
+    code = 0 if axis == "x" else oracle.NCODE // 4
+    for m in range(-3, 12):
+        for n in range(-3, 24):
+            a = x0 + m * lam   # along the direction
+            b = 0.1 + n * r    # across
+            xu, yu = (a, b) if axis == "x" else (b, a)
+            recs.append(rec(int(round(xu * UNIT)), int(round(yu * UNIT)), code))
+    recs = np.array(recs)
+    # exact positions after rounding to units
+    h = o.splat(0, recs)
+    p = s.patches[0]
+    xc = (np.arange(p.nx) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, xc)
+    along = X if axis == "x" else Y
+    x0u = round(x0 * UNIT) / UNIT
+    want = A * np.cos(math.pi * (along - x0u) / r)
+    # lattice rounding to 2^-20 m is below 1e-6 of a radius
+    assert np.max(np.abs(h - want)) <= 1e-5 * A
+
+
+def test_single_pair_moments():
+    """Crest volume of the raised-cosine product is A (r/dx)^2 per cell area
+    when 2r/dx is an integer; the pair has zero volume and first moment
+    A (r/dx)^2 r along its direction (trough one radius behind)."""
+    s = pin_scene()
+    o = oracle.Oracle(s)
+    r = o.bucket(0)["r"]
+    A = o.patch_bucket(0, 0)["A"]
+    p = s.patches[0]
+    xc = (np.arange(p.nx) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, xc)
+    for code, ux, uy in ((0, 1, 0), (oracle.NCODE // 4, 0, 1), (oracle.NCODE // 2, -1, 0)):
+        px, py = 8.13, 7.71
+        h = o.splat(0, np.array([rec(int(px * UNIT), int(py * UNIT), code)]))
+        vol = (r / p.dx) ** 2 * A
+        assert abs(h.sum()) <= 1e-12 * vol
+        mx = (h * X).sum()
+        my = (h * Y).sum()
+        assert mx == pytest.approx(vol * r * ux, abs=1e-9 * vol)
+        assert my == pytest.approx(vol * r * uy, abs=1e-9 * vol)
+        # positive lobe of the crest alone equals the crest volume when the
+        # trough does not overlap: check the crest peak value
+        i = np.unravel_index(np.argmax(h), h.shape)
+        assert h[i] <= A + 1e-15
+
+
+def test_single_particle_closed_form():
+    """One particle at direction theta: h = A [w(dx) w(dy) - w(dx + r cos) w(dy + r sin)]."""
+    s = pin_scene()
+    o = oracle.Oracle(s)
+    r = o.bucket(0)["r"]
+    A = o.patch_bucket(0, 0)["A"]
+    p = s.patches[0]
+    code = 1234
+    th = 2 * math.pi * code / oracle.NCODE
+    xu, yu = 8_000_001, 8_400_003
+    h = o.splat(0, np.array([rec(xu, yu, code)]))
+    xc = (np.arange(p.nx) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, xc)
+
+    def w(d):
+        return np.where(np.abs(d) < r, 0.5 * (1 + np.cos(np.pi * d / r)), 0.0)
+
+    dx_, dy_ = X - xu / UNIT, Y - yu / UNIT
+    want = A * (w(dx_) * w(dy_) - w(dx_ + r * math.cos(th)) * w(dy_ + r * math.sin(th)))
+    assert np.max(np.abs(h - want)) <= 1e-14
+
+
+# ---------------------------------------------------------------- blend
+def test_blend_limits_and_bilinear():
+    """Sec 3.1 local replacement: a vanishing blend band gives the pure WP map
+    inside the patch; an unbounded band gives the background sampled by
+    bilinear interpolation at the cell's world position (exact for a field
+    linear in the grid index, away from the periodic wrap)."""
+    H = np.zeros((64, 64))
+    jy, jx = np.mgrid[0:64, 0:64]
+    H[:] = 0.01 * jx - 0.02 * jy + 0.3
+    s = scenes.c1()
+    s.patches[0].blend_band = 1e-9
+    o = oracle.Oracle(s)
+    o.step(3)
+    raw, bl = o.patch_maps(0, H)
+    assert np.array_equal(raw, bl)
+    s = scenes.c1()
+    s.patches[0].blend_band = 1e12
+    o = oracle.Oracle(s)
+    o.step(3)
+    raw, bl = o.patch_maps(0, H)
+    p = s.patches[0]
+    dxf = s.fft_L / s.fft_n
+    X = p.anchor_x + (np.arange(p.nx) + 0.5) * p.dx
+    Y = p.anchor_y + (np.arange(p.ny) + 0.5) * p.dx
+    XX, YY = np.meshgrid(X, Y)
+    want = 0.01 * XX / dxf - 0.02 * YY / dxf + 0.3
+    assert np.max(np.abs(bl - want)) <= 1e-12
+
+
+def test_blend_profile():
+    """Default band: weight 1 (pure WP) at depth >= band, smooth rise from
+    ~0 at the border, monotone in depth."""
+    s = scenes.c1()
+    o = oracle.Oracle(s)
+    o.step(0)
+    H = np.ones((64, 64))
+    raw, bl = o.patch_maps(0, H)   # no particles: raw = 0, blended = 1 - w
+    p = s.patches[0]
+    band = o.patch_bucket(0, 0)["band"]
+    i = np.arange(p.nx)
+    d = np.minimum(i + 0.5, p.nx - i - 0.5) * p.dx
+    row = bl[p.ny // 2]            # depth along x only in the middle row
+    deep = d >= band
+    assert np.all(row[deep] == 0.0)
+    sh = ~deep
+    assert np.all(row[sh] > 0) and np.all(row[sh] < 1)
+    # outermost cell: 1 - w >= 1 - 3 (dx / 2 band)^2
+    assert row[0] >= 1 - 3 * (0.5 * p.dx / band) ** 2
+    half = row[: p.nx // 2]
+    assert np.all(np.diff(half) <= 0)
+
+
+# ---------------------------------------------------------------- kinematics
+def positions(o, P, n):
+    out = np.zeros((P.shape[0], 2), dtype=np.int64)
+    for k, q in enumerate(P):
+        vx, vy = o.velocity(int(q[1]), int(q[4]))
+        age = n - q[5]
+        out[k, 0] = q[6] + ((age * vx) >> 12)
+        out[k, 1] = q[7] + ((age * vy) >> 12)
+    return out
+
+
+def test_propagation_and_survival_window():
+    """Positions advance at the bucket phase speed c_i = g / w_i (Sec 3.2) to
+    within the fixed-point rounding, and every live particle lies inside its
+    window expanded by 2 r."""
+    s = scenes.c2()
+    o = oracle.Oracle(s)
+    o.step(120)
+    P = o.particles()
+    assert P.shape[0] > 10000
+    n = o.n
+    pos = positions(o, P, n)
+    wx, wy = o.window(0)
+    dxu = int(s.patches[0].dx * UNIT)
+    sel = np.random.default_rng(0).choice(P.shape[0], 3000, replace=False)
+    for k in sel:
+        q = P[k]
+        b = o.bucket(int(q[1]))
+        age = n - q[5]
+        th = 2 * math.pi * q[4] / oracle.NCODE
+        ex = q[6] + age * b["c"] * s.dt * math.cos(th) * UNIT
+        ey = q[7] + age * b["c"] * s.dt * math.sin(th) * UNIT
+        assert abs(pos[k, 0] - ex) <= 1 + age * 0.5 / 4096
+        assert abs(pos[k, 1] - ey) <= 1 + age * 0.5 / 4096
+        m = b["margin_u"]
+        assert wx * dxu - m <= pos[k, 0] <= (wx + s.patches[0].nx) * dxu + m
+        assert wy * dxu - m <= pos[k, 1] <= (wy + s.patches[0].ny) * dxu + m
+
+
+def test_entry_side_matches_direction():
+    """Boundary particles enter through the side they travel away from."""
+    s = scenes.c1()
+    o = oracle.Oracle(s)
+    o.step(5)
+    P = o.particles()
+    new = P[(P[:, 5] == 5) & (P[:, 2] == 0)]
+    assert new.shape[0] > 50
+    dxu = int(s.patches[0].dx * UNIT)
+    W = s.patches[0].nx * dxu
+    for q in new:
+        vx, vy = o.velocity(int(q[1]), int(q[4]))
+        on_l, on_r = q[6] == 0, q[6] == W
+        on_b, on_t = q[7] == 0, q[7] == W
+        assert on_l or on_r or on_b or on_t
+        if on_l:
+            assert vx > 0 or on_b or on_t
+        if on_r:
+            assert vx <= 0 or on_b or on_t
+        if on_b:
+            assert vy > 0 or on_l or on_r
+        if on_t:
+            assert vy <= 0 or on_l or on_r
+
+
+def test_inverse_cdf_direction_frequencies():
+    """Directions are drawn from Dir (Sec 4.2): chi-square of the bin
+    frequencies of freshly injected particles against q / Q."""
+    s = scenes.c1()
+    s.spectrum.eta = 1000.0
+    o = oracle.Oracle(s)
+    q, cdf, codes = o.dir_table(0)
+    counts = np.zeros(64)
+    code_to_bin = {int(c): b for b, c in enumerate(codes)}
+    for n in range(1, 9):
+        o.step(1)
+        P = o.particles()
+        new = P[(P[:, 5] == n) & (P[:, 1] == 0)]
+        for c in new[:, 4]:
+            counts[code_to_bin[int(c)]] += 1
+    tot = counts.sum()
+    assert tot > 20000
+    exp = tot * q / q.sum()
+    keep = exp >= 5
+    obs = np.append(counts[keep], counts[~keep].sum())
+    ex = np.append(exp[keep], exp[~keep].sum())
+    chi2 = ((obs - ex) ** 2 / ex).sum()
+    dof = obs.size - 1
+    assert stats.chi2.sf(chi2, dof) > 1e-4
+    assert counts[~(q > 0)].sum() == 0
+
+
+def test_count_conservation_and_histogram():
+    """Per bucket: live = injected + emitted + 2 x subdivided - died, and the
+    bin histogram sums to the live count on the stated bin grid."""
+    s = scenes.c2()
+    o = oracle.Oracle(s)
+    o.step(400)
+    c = o.counts(0)
+    live = c[:, 0]
+    assert np.array_equal(live, c[:, 1] + c[:, 2] + 2 * c[:, 3] - c[:, 4])
+    assert c[:, 3].sum() > 0   # splits happened
+    P = o.particles()
+    for b in range(o.nb):
+        assert (P[:, 1] == b).sum() == live[b]
+        binw, nbx, nby = o.tile_dims(0, b)
+        m = o.bucket(b)["margin_u"]
+        dxu = int(s.patches[0].dx * UNIT)
+        assert nbx == (s.patches[0].nx * dxu + 2 * m) // (binw * dxu) + 1
+        assert o.tiles(0, b).sum() == live[b]
+
+
+def test_emission_count():
+    """A source emits a ring of n_e particles every E steps, from step 1."""
+    s = scenes.c2()
+    o = oracle.Oracle(s)
+    E = o.source_info(0)["E"]
+    o.step(100)
+    b = o.source_info(0)["bucket"]
+    assert o.counts(0)[b, 2] == 64 * math.ceil(100 / E)
+
+
+def test_subdivision_conserves_amplitude():
+    """A split replaces a particle of amplitude B m 3^-L by three of
+    B m 3^-(L+1) at codes c and c +- a0 / 3^(L+1): each complete family (one
+    ring slot of one emission) keeps total amplitude B m and a code set
+    symmetric about the slot direction."""
+    s = scenes.c2()
+    o = oracle.Oracle(s)
+    si = o.source_info(0)
+    o.step(si["T"][0] + 40)
+    P = o.particles()
+    src = P[P[:, 2] == 1]
+    assert (src[:, 3] >= 1).any()
+    fam = {}
+    for q in src:
+        fam.setdefault((int(q[5]), int(q[9])), []).append(q)
+    a0 = si["a0"]
+    checked = 0
+    for (birth, slot), qs in fam.items():
+        levels = {int(q[3]) for q in qs}
+        assert len(levels) == 1
+        L = levels.pop()
+        if len(qs) != 3 ** L:
+            continue  # part of the family has left the window
+        tot = sum(3.0 ** -int(q[3]) for q in qs)
+        assert tot == pytest.approx(1.0, rel=1e-14)
+        offs = sorted(((int(q[4]) - slot * a0 + oracle.NCODE // 2) % oracle.NCODE) - oracle.NCODE // 2
+                      for q in qs)
+        assert offs == sorted(-x for x in offs)
+        step = a0 // 3 ** L if L else a0
+        if L:
+            assert all(x % step == 0 for x in offs)
+        checked += 1
+    assert checked > 10
