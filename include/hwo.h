@@ -1,0 +1,167 @@
+/* hwo.h -- C ABI of the MI355X hybrid-ocean hot path.
+ *
+ * Per frame the library computes, on one gfx950 GPU (Xue et al., "Real-Time
+ * Interactive Hybrid Ocean: Spectrum-Consistent Wave Particle-FFT Coupling",
+ * arXiv 2511.02852):
+ *   (a) the FFT background: directional JONSWAP spectrum (Sec 3.1, Eq 1-6),
+ *       evolved under deep-water dispersion and inverse-transformed (Sec 4.1);
+ *   (b) boundary injection of wave particles into every patch, per frequency
+ *       bucket, with counts from Eq "result_2" and directions drawn from the
+ *       same directional spectrum (Sec 3.3, Sec 4.2);
+ *   (c) propagation at each bucket's phase speed c_i = g / w_i (Sec 3.2),
+ *       ring emission from moving sources into the closest-radius bucket
+ *       (Sec 4.3) and 3-way subdivision of ring particles;
+ *   (d) the per-bucket splat of the raised-cosine crest/trough particle pair
+ *       (Fig 1, Sec 4.2) into patch height maps, layers summed;
+ *   (e) the blend of each patch map with the background (Sec 3.1, Sec 4.2).
+ *
+ * Conventions
+ *   - Every function returns an int status: HWO_OK (0) or a negative code;
+ *     hwo_last_error() gives a message.  No exception crosses the ABI.
+ *   - The library owns all device state (allocated through the caller's
+ *     allocator if given).  The caller owns every destination buffer.
+ *   - Scene calls (set_spectrum, add_patch, add_source, set_bins) must come
+ *     before the first step; afterwards they fail with HWO_ESTATE.
+ *   - hwo_step is asynchronous on the library stream; read_* calls
+ *     synchronise that stream.  One handle must not be used from two threads
+ *     at once.
+ *   - Patch and source ids are dense, in call order; they select the RNG
+ *     streams, so the same scene and seed always give the same particles.
+ */
+#ifndef HWO_H
+#define HWO_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    HWO_OK = 0,
+    HWO_EINVAL = -1,    /* bad argument */
+    HWO_ESTATE = -2,    /* call out of order */
+    HWO_ENOMEM = -3,    /* allocation failed */
+    HWO_EDEVICE = -4,   /* HIP runtime error */
+    HWO_ERANGE = -5,    /* buffer too small / index out of range */
+    HWO_EOVERFLOW = -6  /* particle capacity exceeded (counts still valid) */
+};
+
+typedef struct hwo_ocean hwo_ocean;
+
+/* Device allocator hooks: alloc(bytes, ctx) returns a device pointer or NULL;
+ * free(ptr, ctx) releases it.  NULL hooks select hipMalloc / hipFree. */
+typedef void *(*hwo_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*hwo_free_fn)(void *ptr, void *ctx);
+
+typedef struct {
+    int32_t fft_n;          /* background grid N (power of two, 16..4096) */
+    double fft_L;           /* background period (m) */
+    double g;               /* gravity (m/s^2) */
+    double dt;              /* step (s); heights after step n describe t = n dt */
+    uint64_t seed;          /* Philox key for h0 and injection draws */
+    int32_t compact;        /* 0: 32-byte particle records, 1: 16-byte records */
+    int32_t batched;        /* 0: launches per patch; 1: one launch per stage for
+                               all patches, whole frame replayed as a hipGraph */
+    void *stream;           /* hipStream_t to run on; NULL: the library creates one */
+    hwo_alloc_fn dev_alloc; /* optional device allocator */
+    hwo_free_fn dev_free;
+    void *alloc_ctx;
+    int64_t max_particles;  /* particle capacity; 0 selects an estimate */
+} hwo_config;
+
+/* Spectrum and bucket parameters (Sec 3.1, Sec 3.3). */
+typedef struct {
+    double U10, fetch;      /* wind speed at 10 m (m/s), fetch (m) -- Eq 4 */
+    double gamma;           /* peak enhancement; <= 0: Eq 4 */
+    double spread_s;        /* cos-2s exponent; < 0: Mitsuyasu s(w), Eq 6 */
+    double wind_dir;        /* radians from +x */
+    int32_t n_buckets;      /* 1..16 log-spaced wavelength buckets */
+    double lambda_min, lambda_max; /* bucket wavelength range (m) */
+    double eta;             /* particles per injected group (paper N_theta) */
+    int32_t max_level;      /* subdivision levels of ring particles, 0..4 */
+    double subdiv_frac;     /* split when ring spacing > subdiv_frac * radius */
+    int32_t h0_mode;        /* 0 Gaussian h0, 1 unit modulus */
+} hwo_spectrum;
+
+typedef struct {
+    double anchor_x, anchor_y; /* world position (m) of the patch frame origin */
+    int32_t nx, ny;         /* cells; max 4096 each */
+    double dx;              /* cell size (m); dx * 2^20 must be an even integer */
+    double eta;             /* <= 0: spectrum eta */
+    double blend_band;      /* <= 0: min(largest radius, min side / 4) */
+    int32_t follow;         /* source id that recentres the window, -1 static */
+} hwo_patch;
+
+typedef struct {
+    double x0, y0;          /* world start (m) */
+    double vx, vy;          /* velocity (m/s); zero speed emits nothing */
+    double radius, draft;   /* disc radius and draft (m) */
+    int32_t ring_n;         /* particles per ring; must divide 128 */
+    int32_t patch;          /* patch receiving the particles */
+} hwo_source;
+
+/* Create a handle.  Validates the config; allocates nothing on the device. */
+int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out);
+void hwo_destroy_ocean(hwo_ocean *o);
+const char *hwo_last_error(const hwo_ocean *o);
+
+/* Spectrum, buckets, direction tables, h0(k) and twiddles (FP64 on the GPU,
+ * stored FP32).  Once per handle, before add_patch / add_source. */
+int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp);
+/* Add a patch (max 127); *id receives its index. */
+int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id);
+/* Add a moving source (max 127) emitting into patch src->patch. */
+int hwo_add_source(hwo_ocean *o, const hwo_source *s, int32_t *id);
+/* Per-bucket particle bin edge in cells (n == n_buckets, each 1..4096).
+ * Optional; changes only the bin histogram, never heights or other counts. */
+int hwo_set_bins(hwo_ocean *o, const int32_t *bin_cells, int32_t n);
+
+/* Advance nsteps frames (asynchronous).  The first call allocates device
+ * memory and fixes the scene. */
+int hwo_step(hwo_ocean *o, int32_t nsteps);
+int hwo_sync(hwo_ocean *o);
+int64_t hwo_step_index(const hwo_ocean *o);
+
+/* Copy a height map (FP32, row-major [y][x]) into dst (host or device memory
+ * per dst_is_device).  which = -1: background N x N; which = p >= 0: patch p
+ * (ny x nx) with layer 0 = blended, 1 = raw wave-particle height.  Syncs. */
+int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst,
+                        int64_t dst_elems, int32_t dst_is_device);
+
+/* Per bucket of patch p, six int64: live, injected, emitted, subdivided,
+ * died, dropped (capacity overflow, whole ocean).  dst_elems >= 6 n_buckets.
+ * Returns HWO_EOVERFLOW (with valid counts) if particles were dropped. */
+int hwo_read_counts(hwo_ocean *o, int32_t patch, int64_t *dst, int64_t dst_elems);
+
+/* Bin grid of (patch, bucket): dims = {bin edge cells, nbx, nby}. */
+int hwo_tile_dims(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dims);
+/* Live particles per bin, row-major [by][bx], bins anchored at the window
+ * origin minus the bucket margin 2 r. */
+int hwo_read_tiles(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dst, int64_t n);
+
+/* Live particles as canonical records of 10 int64:
+ * patch, bucket, kind (0 boundary, 1 ring), level, code (units of
+ * 2 pi / 10368), birth step, origin x, origin y (2^-20 m from the patch
+ * anchor), source (-1 boundary), ring slot.  *n_out receives the count;
+ * fails with HWO_ERANGE if max_recs is too small. */
+int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_out);
+
+/* Test hook: splat caller-placed canonical records into patch p's raw map at
+ * the current step (no binning), result in dst (host, ny x nx). */
+int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, float *dst,
+                   int64_t dst_elems);
+
+/* Per-stage timing (benchmark support).  enable != 0 brackets every kernel
+ * launch with HIP events (graph replay is then disabled); hwo_stage_times
+ * returns accumulated milliseconds and launch counts per stage:
+ *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat */
+int hwo_set_timing(hwo_ocean *o, int32_t enable);
+int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
+/* Bytes of particle storage per record for the active form (16 or 32). */
+int32_t hwo_record_bytes(const hwo_ocean *o);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

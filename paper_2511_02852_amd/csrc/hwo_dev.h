@@ -1,0 +1,248 @@
+// hwo_dev.h -- internal definitions of the gfx950 hybrid-ocean library.
+//
+// Fixed-point conventions (shared as a *format* with the oracle, each side
+// writes its own code):
+//   positions   int32, 2^-20 m units, relative to the patch anchor
+//   velocity    int32 per step, 2^-32 m units; position(age) =
+//               origin + floor(age * V / 4096)
+//   directions  integer codes, 2 pi / 10368 per unit (2 * 64 * 3^4)
+//   rates       32.32 fixed point groups*eta per step; count(n) =
+//               floor(n R / 2^32) - floor((n - 1) R / 2^32)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hwo {
+
+constexpr int kMaxBuckets = 16;
+constexpr int kDirBins = 64;
+constexpr int kMaxLevel = 4;
+constexpr int kNCode = 10368;
+constexpr int kAgeMax = 65535;
+constexpr int kMaxPatches = 127;
+constexpr int kMaxSources = 127;
+constexpr int kMaxRing = 128;
+constexpr uint32_t kNoSource = 127;
+constexpr int kTile = 64;          // splat output tile edge (cells)
+constexpr int kThreads = 256;
+constexpr uint64_t kStreamInject = 1;
+constexpr uint64_t kStreamH0 = 2;
+
+// ---------------------------------------------------------------- records
+// meta word: level 0-2 | kind 3 | bucket 4-7 | patch 8-14 | src 15-21 | slot 22-28
+__host__ __device__ inline uint32_t pack_meta(uint32_t level, uint32_t kind, uint32_t bucket,
+                                              uint32_t patch, uint32_t src, uint32_t slot) {
+  return level | (kind << 3) | (bucket << 4) | (patch << 8) | (src << 15) | (slot << 22);
+}
+__host__ __device__ inline uint32_t m_level(uint32_t m) { return m & 7u; }
+__host__ __device__ inline uint32_t m_kind(uint32_t m) { return (m >> 3) & 1u; }
+__host__ __device__ inline uint32_t m_bucket(uint32_t m) { return (m >> 4) & 15u; }
+__host__ __device__ inline uint32_t m_patch(uint32_t m) { return (m >> 8) & 127u; }
+__host__ __device__ inline uint32_t m_src(uint32_t m) { return (m >> 15) & 127u; }
+__host__ __device__ inline uint32_t m_slot(uint32_t m) { return (m >> 22) & 127u; }
+
+// Plain form: 32 bytes, every attribute a full 32-bit word, amplitude FP32.
+struct RecWide {
+  int32_t ox, oy;
+  int32_t birth;
+  int32_t code;
+  uint32_t meta;
+  float amp;
+  int32_t pad0, pad1;
+};
+// Compact form: 16 bytes; birth modulo 2^16 (ages never exceed 65535) and
+// code share a word; the amplitude is rebuilt from per-patch / per-ring
+// tables, so no attribute is rounded.
+struct RecCompact {
+  int32_t ox, oy;
+  uint32_t bc;   // birth & 0xffff | code << 16
+  uint32_t meta;
+};
+static_assert(sizeof(RecWide) == 32, "wide record");
+static_assert(sizeof(RecCompact) == 16, "compact record");
+
+// Decoded particle.
+struct Part {
+  int32_t ox, oy;
+  int32_t age;     // n - birth (>= 0); 65536 means expired
+  int32_t code;
+  uint32_t meta;
+  float amp;       // wide form only
+};
+
+// ---------------------------------------------------------------- tables
+struct PatchDev {
+  double ax, ay, dx;
+  int32_t nx, ny, dxu, follow;
+  float band, ratio;           // blend band (m); dx / background cell
+  int32_t bin_lo, bin_hi;      // bins of this patch in the global histogram
+  int32_t tile0, ntx, nty;     // splat output tiles
+  int32_t src_lo, src_hi;      // range in the patch-sorted source list
+  int64_t cell0;               // offset of this patch in the height buffers
+  float A[kMaxBuckets];        // boundary amplitude per bucket
+  uint64_t Rx[kMaxBuckets], Ry[kMaxBuckets];
+  int32_t binu[kMaxBuckets];   // bin edge (position units)
+  int32_t nbx[kMaxBuckets], nby[kMaxBuckets], binbase[kMaxBuckets];
+};
+
+struct SourceDev {
+  double x0, y0, vx, vy;
+  float B;
+  int32_t patch, bucket, ne, a0, E, ring0;
+  int32_t T[kMaxLevel];
+};
+
+struct StepPatch {             // per patch, rewritten every step
+  int32_t wx, wy;              // window origin (cells)
+  int32_t gx0, gy0;            // background cell of the first patch cell
+  float fx0, fy0;              // fractional offset, FP64-derived
+  int32_t ex_lo, ex_hi;        // previous particles of this patch in the input buffer
+  int32_t inj_lo, inj_hi;      // new boundary particles
+  int32_t em_lo, em_hi;        // new ring particles
+};
+
+struct Globals {
+  int64_t n;                   // current step
+  int32_t n_live;              // particles in the current buffer (<= capacity)
+  int32_t total;               // live particles counted this step (may exceed capacity)
+  unsigned long long dropped;  // particles lost to capacity, cumulative
+  int32_t err;                 // bit 0: position range exceeded
+  int32_t pad;
+};
+
+enum { CNT_INJ = 0, CNT_EMIT, CNT_SUB, CNT_DIED, CNT_NUM };
+
+// Everything a kernel needs, passed by value.
+struct Dev {
+  int32_t np, ns, nb, N, cap, nbins, ntiles, compact, lmax;
+  int32_t n_inj_slots;         // np * nb * 2
+  double g, dt, L, dxf;
+  uint64_t seed;
+  const PatchDev *patches;
+  const SourceDev *sources;
+  const int32_t *src_order;    // sources sorted by patch
+  const int2 *V;               // [nb][kNCode] velocity per step
+  const float2 *UC;            // [kNCode] unit direction
+  const uint32_t *cdf;         // [nb][64] inclusive integer CDF
+  const uint32_t *cdfQ;        // [nb] totals
+  const int32_t *codes;        // [64] direction code of each bin
+  const float *bucket_r;       // [nb] radius (m)
+  const int32_t *margin;       // [nb] ceil(2 r 2^20)
+  const float *ring_m;         // [sum ne] ring multipliers
+  const int2 *ring_O;          // [sum ne] ring offsets (units)
+  Globals *glob;
+  StepPatch *sp;
+  int32_t *inj_off;            // [n_inj_slots + 1]
+  int32_t *em_off;             // [ns + 1]
+  int2 *src_pos;               // [ns] source position (units, patch frame)
+  unsigned long long *ctr;     // [np][nb][CNT_NUM]
+  int32_t *hist, *off, *cur, *bsum;
+  void *S0, *S1;               // particle buffers; step n reads S[(n-1)&1], writes S[n&1]
+  const float2 *h0T;           // [N][N] h0 transposed: row = kx index
+  const float2 *tw;            // [N] e^{2 pi i k / N}
+  float2 *FT;                  // [N/2+1][N]
+  float *H;                    // [N][N]
+  float *raw, *blend;          // heights, all patches
+};
+
+// ---------------------------------------------------------------- helpers
+__host__ __device__ inline int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b) != 0 && a < 0) q -= 1;
+  return q;
+}
+
+// Round half away from zero, exact for |x| < 2^52 (x - trunc(x) is exact).
+__device__ inline int64_t round_away(double x) {
+  double t = trunc(x);
+  double f = x - t;
+  if (f >= 0.5) t += 1.0;
+  else if (f <= -0.5) t -= 1.0;
+  return (int64_t)t;
+}
+
+// Philox4x64-10 (Salmon et al., SC'11).
+__device__ inline void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += W0; k1 += W1; }
+    uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+    uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+    uint64_t n0 = hi1 ^ c[1] ^ k0;
+    uint64_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+  }
+}
+
+__device__ inline int64_t cum_count(uint64_t R, int64_t n) {
+  uint64_t hi = R >> 32, lo = R & 0xFFFFFFFFull;
+  return (int64_t)((uint64_t)n * hi + (((uint64_t)n * lo) >> 32));
+}
+
+template <class Rec> struct RecIO;
+
+template <> struct RecIO<RecWide> {
+  __device__ static Part load(const RecWide *S, int64_t i, int64_t n) {
+    RecWide r = S[i];
+    Part p;
+    p.ox = r.ox; p.oy = r.oy; p.code = r.code; p.meta = r.meta; p.amp = r.amp;
+    p.age = (int32_t)(n - (int64_t)r.birth);
+    return p;
+  }
+  __device__ static void store(RecWide *S, int64_t i, const Part &p, int64_t n) {
+    RecWide r;
+    r.ox = p.ox; r.oy = p.oy; r.birth = (int32_t)(n - p.age); r.code = p.code; r.meta = p.meta;
+    r.amp = p.amp; r.pad0 = 0; r.pad1 = 0;
+    S[i] = r;
+  }
+  static constexpr bool kHasAmp = true;
+};
+
+template <> struct RecIO<RecCompact> {
+  __device__ static Part load(const RecCompact *S, int64_t i, int64_t n) {
+    RecCompact r = S[i];
+    Part p;
+    p.ox = r.ox; p.oy = r.oy; p.code = (int32_t)(r.bc >> 16); p.meta = r.meta; p.amp = 0.f;
+    uint32_t a = ((uint32_t)n - (r.bc & 0xFFFFu)) & 0xFFFFu;
+    p.age = (int32_t)a;   // 0 for a stored particle means 65536 (expired); callers fix up
+    return p;
+  }
+  __device__ static void store(RecCompact *S, int64_t i, const Part &p, int64_t n) {
+    RecCompact r;
+    r.ox = p.ox; r.oy = p.oy;
+    r.bc = ((uint32_t)(n - p.age) & 0xFFFFu) | ((uint32_t)p.code << 16);
+    r.meta = p.meta;
+    S[i] = r;
+  }
+  static constexpr bool kHasAmp = false;
+};
+
+// Amplitude of a particle: boundary particles carry the patch/bucket
+// amplitude; ring particles B * m_slot / 3^level.
+template <class Rec>
+__device__ inline float particle_amp(const Dev &d, const Part &p) {
+  if (RecIO<Rec>::kHasAmp) return p.amp;
+  uint32_t m = p.meta;
+  if (m_kind(m) == 0) return d.patches[m_patch(m)].A[m_bucket(m)];
+  const SourceDev &s = d.sources[m_src(m)];
+  const float inv3[5] = {1.f, 1.f / 3.f, 1.f / 9.f, 1.f / 27.f, 1.f / 81.f};
+  return s.B * d.ring_m[s.ring0 + m_slot(m)] * inv3[m_level(m)];
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_h0(const Dev &d, float2 *h0T, float2 *tw, double alpha, double wp, double gamma,
+               double s_const, double wind_dir, int h0_mode, hipStream_t st);
+void launch_fft_a(const Dev &d, hipStream_t st);
+void launch_fft_b(const Dev &d, hipStream_t st);
+void launch_params(const Dev &d, hipStream_t st);
+void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st);
+void launch_scan(const Dev &d, int bin_lo, int bin_hi, bool first, bool last, hipStream_t st);
+void launch_splat_tiles(const Dev &d, int t0, int ntiles, hipStream_t st);
+void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw,
+                         int64_t out_off, hipStream_t st);
+void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, hipStream_t st);
+int scan_blocks(int nbins);
+
+}  // namespace hwo

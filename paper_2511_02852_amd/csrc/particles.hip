@@ -1,0 +1,463 @@
+// particles.hip -- per-step wave-particle bookkeeping on gfx950.
+//
+// One step n (heights then describe t_n = n dt):
+//   k_params   one block: advance the step counter, recentre the windows of
+//              patches that follow a source (FP64 source position), compute
+//              the FP64 background offsets of every patch, the boundary
+//              injection count of every (patch, bucket, side pair) from the
+//              32.32 rate of Eq "result_2", the ring emissions of every
+//              source (Sec 4.3), and their prefix sums.
+//   k_update   persistent grid over all work items of the step: previous
+//   <count>    particles (subdivide, then survive), new boundary particles
+//              (Philox draw -> integer inverse CDF of Dir -> entry side ->
+//              position on the side) and new ring particles.  Every output
+//              particle that survives gets a bin key (patch, bucket, by, bx);
+//              runs of equal keys inside a wavefront are merged before the
+//              histogram atomic (input is sorted by key, so runs are long).
+//   k_scan     exclusive scan of the histogram -> bin offsets (and cursors);
+//              clears the histogram for the next step.
+//   k_update   same computation again; each run reserves its slots with one
+//   <scatter>  atomic on the bin cursor and writes the records, so the
+//              output buffer is sorted by bin.
+// Every integer decision (counts, codes, positions, survival, bins) is made
+// in exact integer arithmetic from fixed-point tables built in FP64, so the
+// result matches the CPU oracle bit for bit.
+#include "hwo_dev.h"
+
+namespace hwo {
+
+// ---------------------------------------------------------------- helpers
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exclusive scan of a[0..len) in place by one block; returns the total.
+__device__ int32_t block_scan_excl(int32_t *a, int len, int32_t *s_tmp /* kThreads + 1 */) {
+  const int tid = threadIdx.x;
+  const int chunk = (len + kThreads - 1) / kThreads;
+  const int beg = tid * chunk, end = min(len, beg + chunk);
+  int32_t sum = 0;
+  for (int i = beg; i < end; ++i) sum += a[i];
+  s_tmp[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t acc = 0;
+    for (int i = 0; i < kThreads; ++i) {
+      int32_t v = s_tmp[i];
+      s_tmp[i] = acc;
+      acc += v;
+    }
+    s_tmp[kThreads] = acc;
+  }
+  __syncthreads();
+  int32_t acc = s_tmp[tid];
+  for (int i = beg; i < end; ++i) {
+    int32_t v = a[i];
+    a[i] = acc;
+    acc += v;
+  }
+  __syncthreads();
+  return s_tmp[kThreads];
+}
+
+// ---------------------------------------------------------------- k_params
+__global__ __launch_bounds__(kThreads) void k_params(Dev d) {
+  __shared__ int64_t s_n;
+  __shared__ int32_t s_tmp[kThreads + 1];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    const int64_t n = d.glob->n + 1;
+    d.glob->n = n;
+    s_n = n;
+  }
+  __syncthreads();
+  const int64_t n = s_n;
+  const double tn = (double)n * d.dt;
+
+  // windows, background offsets, previous-particle ranges
+  for (int p = tid; p < d.np; p += kThreads) {
+    const PatchDev &P = d.patches[p];
+    int64_t wx = 0, wy = 0;
+    if (P.follow >= 0) {
+      const SourceDev &S = d.sources[P.follow];
+      const double xs = S.x0 + S.vx * tn;
+      const double ys = S.y0 + S.vy * tn;
+      wx = round_away((xs - P.ax) / P.dx) - P.nx / 2;
+      wy = round_away((ys - P.ay) / P.dx) - P.ny / 2;
+    }
+    StepPatch W;
+    W.wx = (int32_t)wx;
+    W.wy = (int32_t)wy;
+    // keep every window (with a 64 m margin) inside the int32 position range
+    const int64_t lim = (int64_t)1 << 31;
+    const int64_t reach = (int64_t)64 << 20;
+    if (wx * P.dxu - reach < -lim || (wx + P.nx) * P.dxu + reach >= lim ||
+        wy * P.dxu - reach < -lim || (wy + P.ny) * P.dxu + reach >= lim)
+      atomicOr(&d.glob->err, 1);
+    const double X = P.ax + (double)(wx * P.dxu + P.dxu / 2) * (1.0 / 1048576.0);
+    const double Y = P.ay + (double)(wy * P.dxu + P.dxu / 2) * (1.0 / 1048576.0);
+    const double u = X / d.dxf, v = Y / d.dxf;
+    const double fu = floor(u), fv = floor(v);
+    const int64_t N = d.N;
+    W.gx0 = (int32_t)((((int64_t)fu % N) + N) % N);
+    W.gy0 = (int32_t)((((int64_t)fv % N) + N) % N);
+    W.fx0 = (float)(u - fu);
+    W.fy0 = (float)(v - fv);
+    W.ex_lo = min(d.off[P.bin_lo], d.cap);
+    W.ex_hi = min(d.off[P.bin_hi], d.cap);
+    d.sp[p] = W;
+  }
+
+  // injection counts per (patch, bucket, pair), in that order
+  const int ns_inj = d.n_inj_slots;
+  for (int q = tid; q < ns_inj; q += kThreads) {
+    const int p = q / (2 * d.nb), i = (q / 2) % d.nb, pair = q & 1;
+    const PatchDev &P = d.patches[p];
+    const uint64_t R = pair ? P.Ry[i] : P.Rx[i];
+    d.inj_off[q] = (int32_t)(cum_count(R, n) - cum_count(R, n - 1));
+  }
+  // ring emissions in patch-sorted source order
+  for (int k = tid; k < d.ns; k += kThreads) {
+    const int s = d.src_order[k];
+    const SourceDev &S = d.sources[s];
+    const bool emit = S.E > 0 && ((n - 1) % S.E) == 0;
+    d.em_off[k] = emit ? S.ne : 0;
+    if (emit) {
+      const PatchDev &P = d.patches[S.patch];
+      const double xs = S.x0 + S.vx * tn;
+      const double ys = S.y0 + S.vy * tn;
+      d.src_pos[s] = make_int2((int32_t)round_away((xs - P.ax) * 1048576.0),
+                               (int32_t)round_away((ys - P.ay) * 1048576.0));
+    }
+  }
+  __syncthreads();
+  // counters of created particles (before the scan overwrites the counts)
+  for (int q = tid; q < d.np * d.nb; q += kThreads) {
+    const int c = d.inj_off[2 * q] + d.inj_off[2 * q + 1];
+    if (c) d.ctr[(size_t)q * CNT_NUM + CNT_INJ] += (unsigned long long)c;
+  }
+  for (int k = tid; k < d.ns; k += kThreads) {
+    const int s = d.src_order[k];
+    const SourceDev &S = d.sources[s];
+    if (d.em_off[k]) atomicAdd(&d.ctr[((size_t)S.patch * d.nb + S.bucket) * CNT_NUM + CNT_EMIT], (unsigned long long)S.ne);
+  }
+  __syncthreads();
+  const int32_t tot_inj = block_scan_excl(d.inj_off, ns_inj, s_tmp);
+  if (tid == 0) d.inj_off[ns_inj] = tot_inj;
+  const int32_t tot_em = block_scan_excl(d.em_off, d.ns, s_tmp);
+  if (tid == 0) d.em_off[d.ns] = tot_em;
+  __syncthreads();
+  for (int p = tid; p < d.np; p += kThreads) {
+    const PatchDev &P = d.patches[p];
+    StepPatch &W = d.sp[p];
+    W.inj_lo = d.inj_off[p * 2 * d.nb];
+    W.inj_hi = d.inj_off[(p + 1) * 2 * d.nb];
+    W.em_lo = d.em_off[P.src_lo];
+    W.em_hi = d.em_off[P.src_hi];
+  }
+}
+
+// ---------------------------------------------------------------- update
+// Survival and bin key of a particle at age `age` (>= 0).  -1 if it dies.
+__device__ __forceinline__ int32_t survive_key(const Dev &d, const PatchDev &P, const StepPatch &W,
+                                               int bucket, int code, int32_t ox, int32_t oy, int32_t age) {
+  if (age > kAgeMax) return -1;
+  const int2 v = d.V[bucket * kNCode + code];
+  const int64_t px = (int64_t)ox + (((int64_t)age * v.x) >> 12);
+  const int64_t py = (int64_t)oy + (((int64_t)age * v.y) >> 12);
+  const int64_t m = d.margin[bucket];
+  const int64_t lox = (int64_t)W.wx * P.dxu - m, hix = (int64_t)(W.wx + P.nx) * P.dxu + m;
+  const int64_t loy = (int64_t)W.wy * P.dxu - m, hiy = (int64_t)(W.wy + P.ny) * P.dxu + m;
+  if (px < lox || px > hix || py < loy || py > hiy) return -1;
+  const uint32_t binu = (uint32_t)P.binu[bucket];
+  const uint32_t bx = (uint32_t)(px - lox) / binu;
+  const uint32_t by = (uint32_t)(py - loy) / binu;
+  return P.binbase[bucket] + (int32_t)(by * (uint32_t)P.nbx[bucket] + bx);
+}
+
+// Wave-level run merge: lanes with equal consecutive keys form a run.
+// Returns for each valid lane its head lane and rank in the run; heads also
+// get the run length.
+struct Run {
+  int head, rank, len;
+  bool is_head;
+};
+__device__ __forceinline__ Run wave_runs(int32_t key) {
+  const int lane = (int)__lane_id();
+  const int32_t prev = __shfl_up(key, 1);
+  const bool valid = key >= 0;
+  const bool h = valid && (lane == 0 || prev != key);
+  const uint64_t hm = __ballot(h);
+  const uint64_t bm = __ballot(h || !valid);
+  Run r;
+  const uint64_t below = hm & ((2ull << lane) - 1ull);
+  r.head = below ? 63 - __clzll((long long)below) : 0;
+  r.rank = lane - r.head;
+  const uint64_t above = bm & ~((2ull << lane) - 1ull);
+  const int next = above ? (__ffsll((long long)above) - 1) : 64;
+  r.len = next - lane;
+  r.is_head = h;
+  return r;
+}
+
+template <class Rec, bool kScatter>
+__global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
+  const int64_t n = d.glob->n;
+  const Rec *__restrict__ Sin = (const Rec *)(((n - 1) & 1) ? d.S1 : d.S0);
+  Rec *__restrict__ Sout = (Rec *)((n & 1) ? d.S1 : d.S0);
+  const StepPatch A = d.sp[p0], B = d.sp[p1 - 1];
+  const int ex0 = A.ex_lo, nex = max(0, B.ex_hi - A.ex_lo);
+  const int in0 = A.inj_lo, ninj = B.inj_hi - A.inj_lo;
+  const int em0 = A.em_lo, nem = B.em_hi - A.em_lo;
+  const int total = nex + ninj + nem;
+  const int lane = (int)__lane_id();
+
+  for (int base = blockIdx.x * kThreads; base < total; base += gridDim.x * kThreads) {
+    const int k = base + (int)threadIdx.x;
+    Part o[3];
+    int32_t key[3] = {-1, -1, -1};
+    int nout = 0;
+    int pid = 0, bkt = 0;
+    if (k < nex) {
+      // ---- a previous particle: subdivide, then survive
+      Part q = RecIO<Rec>::load(Sin, ex0 + k, n);
+      if (!RecIO<Rec>::kHasAmp && q.age == 0) q.age = 65536;   // 16-bit birth wrapped: expired
+      pid = (int)m_patch(q.meta);
+      bkt = (int)m_bucket(q.meta);
+      o[0] = q;
+      nout = 1;
+      const uint32_t lev = m_level(q.meta);
+      if (m_kind(q.meta) == 1 && (int)lev < d.lmax) {
+        const SourceDev &S = d.sources[m_src(q.meta)];
+        if (q.age >= S.T[lev]) {
+          int off = S.a0;
+          for (uint32_t l = 0; l <= lev; ++l) off /= 3;
+          o[0].meta = (q.meta & ~7u) | (lev + 1);
+          o[0].amp = q.amp * (1.0f / 3.0f);
+          o[1] = o[0];
+          o[2] = o[0];
+          o[1].code = (q.code - off + kNCode) % kNCode;
+          o[2].code = (q.code + off) % kNCode;
+          nout = 3;
+          if (!kScatter) atomicAdd(&d.ctr[((size_t)pid * d.nb + bkt) * CNT_NUM + CNT_SUB], 1ull);
+        }
+      }
+    } else if (k < nex + ninj) {
+      // ---- a new boundary particle
+      const int gi = in0 + (k - nex);
+      int lo = 0, hi = d.n_inj_slots;   // last slot with inj_off[slot] <= gi
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.inj_off[mid] <= gi) lo = mid; else hi = mid;
+      }
+      const int slot = lo, j = gi - d.inj_off[slot];
+      pid = slot / (2 * d.nb);
+      bkt = (slot / 2) % d.nb;
+      const int pair = slot & 1;
+      uint64_t c[4] = {(uint64_t)pid, (uint64_t)(bkt * 2 + pair), (uint64_t)n, (uint64_t)j};
+      philox4x64(c, d.seed, kStreamInject);
+      const uint32_t Q = d.cdfQ[bkt];
+      const uint32_t t = (uint32_t)__umul64hi(c[0], (uint64_t)Q);
+      const uint32_t *cdf = d.cdf + bkt * kDirBins;
+      int b = 0;   // smallest bin with t < cdf[b]
+      for (int step = 32; step > 0; step >>= 1)
+        if (cdf[b + step - 1] <= t) b += step;
+      const int code = d.codes[b];
+      const PatchDev &P = d.patches[pid];
+      const StepPatch W = d.sp[pid];
+      const int2 v = d.V[bkt * kNCode + code];
+      Part q;
+      if (pair == 0) {
+        q.ox = (v.x > 0) ? W.wx * P.dxu : (W.wx + P.nx) * P.dxu;
+        q.oy = W.wy * P.dxu + (int32_t)__umul64hi(c[1], (uint64_t)P.ny * (uint64_t)P.dxu);
+      } else {
+        q.oy = (v.y > 0) ? W.wy * P.dxu : (W.wy + P.ny) * P.dxu;
+        q.ox = W.wx * P.dxu + (int32_t)__umul64hi(c[1], (uint64_t)P.nx * (uint64_t)P.dxu);
+      }
+      q.age = 0;
+      q.code = code;
+      q.meta = pack_meta(0, 0, bkt, pid, kNoSource, 0);
+      q.amp = P.A[bkt];
+      o[0] = q;
+      nout = 1;
+    } else if (k < total) {
+      // ---- a new ring particle
+      const int gi = em0 + (k - nex - ninj);
+      int lo = 0, hi = d.ns;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (d.em_off[mid] <= gi) lo = mid; else hi = mid;
+      }
+      const int s = d.src_order[lo];
+      const int j = gi - d.em_off[lo];
+      const SourceDev &S = d.sources[s];
+      const int2 sp = d.src_pos[s];
+      const int2 O = d.ring_O[S.ring0 + j];
+      pid = S.patch;
+      bkt = S.bucket;
+      Part q;
+      q.ox = sp.x + O.x;
+      q.oy = sp.y + O.y;
+      q.age = 0;
+      q.code = j * S.a0;
+      q.meta = pack_meta(0, 1, bkt, pid, s, j);
+      q.amp = S.B * d.ring_m[S.ring0 + j];
+      o[0] = q;
+      nout = 1;
+    }
+    if (nout) {
+      const PatchDev &P = d.patches[pid];
+      const StepPatch W = d.sp[pid];
+      for (int r = 0; r < nout; ++r) {
+        key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age);
+        if (!kScatter && key[r] < 0)
+          atomicAdd(&d.ctr[((size_t)pid * d.nb + bkt) * CNT_NUM + CNT_DIED], 1ull);
+      }
+    }
+    // merge runs of equal keys, one atomic per run
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (r > 0 && __ballot(key[r] >= 0) == 0ull) continue;
+      const Run run = wave_runs(key[r]);
+      if (!kScatter) {
+        if (run.is_head) atomicAdd(&d.hist[key[r]], run.len);
+      } else {
+        int32_t basepos = 0;
+        if (run.is_head) basepos = atomicAdd(&d.cur[key[r]], run.len);
+        basepos = __shfl(basepos, run.head);
+        if (key[r] >= 0) {
+          const int32_t slotpos = basepos + run.rank;
+          if (slotpos < d.cap)
+            RecIO<Rec>::store(Sout, slotpos, o[r], n);
+          else
+            atomicAdd(&d.glob->dropped, 1ull);
+        }
+      }
+    }
+    (void)lane;
+  }
+}
+
+// ---------------------------------------------------------------- scan
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = kThreads * kScanPer;
+
+int scan_blocks(int nbins) { return (nbins + kScanChunk - 1) / kScanChunk; }
+
+__global__ __launch_bounds__(kThreads) void k_scan_a(Dev d, int lo, int hi) {
+  __shared__ int32_t s[kThreads];
+  const int beg = lo + blockIdx.x * kScanChunk;
+  int32_t sum = 0;
+  for (int i = beg + threadIdx.x; i < min(hi, beg + kScanChunk); i += kThreads) sum += d.hist[i];
+  s[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) d.bsum[blockIdx.x] = s[0];
+}
+
+// Block b: prefix of the block sums before it, then an exclusive scan of
+// its chunk (each thread 8 consecutive bins, wave scans via shuffles).
+__global__ __launch_bounds__(kThreads) void k_scan_b(Dev d, int lo, int hi, int first, int last) {
+  __shared__ int32_t s_w[kThreads / 64 + 1];
+  __shared__ int32_t s_pre;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // prefix of earlier blocks
+  int32_t pre = 0;
+  for (int i = tid; i < (int)blockIdx.x; i += kThreads) pre += d.bsum[i];
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o);
+  if (lane == 0) s_w[wv] = pre;
+  __syncthreads();
+  if (tid == 0) {
+    int32_t base = first ? 0 : d.off[lo];
+    for (int w = 0; w < kThreads / 64; ++w) base += s_w[w];
+    s_pre = base;
+  }
+  __syncthreads();
+  const int32_t start = s_pre;
+  const int beg = lo + blockIdx.x * kScanChunk + tid * kScanPer;
+  int32_t v[kScanPer];
+  int32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int i = beg + k;
+    v[k] = (i < hi) ? d.hist[i] : 0;
+    sum += v[k];
+  }
+  // inclusive scan of per-thread sums across the wave
+  int32_t inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  __syncthreads();
+  if (lane == 63) s_w[wv] = inc;
+  __syncthreads();
+  int32_t wpre = 0;
+  for (int w = 0; w < wv; ++w) wpre += s_w[w];
+  int32_t acc = start + wpre + inc - sum;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int i = beg + k;
+    if (i < hi) {
+      d.off[i] = acc;
+      d.cur[i] = acc;
+      d.hist[i] = 0;
+    }
+    acc += v[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && tid == kThreads - 1) {
+    // acc now holds the running total after the last bin of this block
+    d.off[hi] = acc;
+    if (last) {
+      d.glob->total = acc;
+      d.glob->n_live = min(acc, d.cap);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- CDF
+// One wavefront per bucket: inclusive scan of the 64 integer direction
+// weights (exact), giving the inverse-CDF table of Dir for injection.
+__global__ void k_cdf(const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ) {
+  const int b = blockIdx.x, lane = threadIdx.x;
+  uint32_t v = q[b * kDirBins + lane];
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(v, o);
+    if (lane >= o) v += y;
+  }
+  cdf[b * kDirBins + lane] = v;
+  if (lane == 63) cdfQ[b] = v;
+}
+
+void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, hipStream_t st) {
+  hipLaunchKernelGGL(k_cdf, dim3(d.nb), dim3(64), 0, st, q, cdf, cdfQ);
+}
+
+// ---------------------------------------------------------------- launchers
+void launch_params(const Dev &d, hipStream_t st) {
+  hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, st, d);
+}
+
+void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st) {
+  if (d.compact) {
+    if (scatter) hipLaunchKernelGGL((k_update<RecCompact, true>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+    else hipLaunchKernelGGL((k_update<RecCompact, false>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+  } else {
+    if (scatter) hipLaunchKernelGGL((k_update<RecWide, true>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+    else hipLaunchKernelGGL((k_update<RecWide, false>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+  }
+}
+
+void launch_scan(const Dev &d, int lo, int hi, bool first, bool last, hipStream_t st) {
+  const int nblk = scan_blocks(hi - lo);
+  if (nblk > 1) hipLaunchKernelGGL(k_scan_a, dim3(nblk), dim3(kThreads), 0, st, d, lo, hi);
+  hipLaunchKernelGGL(k_scan_b, dim3(nblk > 0 ? nblk : 1), dim3(kThreads), 0, st, d, lo, hi, first ? 1 : 0,
+                     last ? 1 : 0);
+}
+
+}  // namespace hwo

@@ -1,0 +1,906 @@
+// runtime.hip -- host side of the hybrid-ocean library: the C ABI of
+// include/hwo.h, the FP64 setup tables, device memory, launch sequencing and
+// hipGraph replay of a frame.
+//
+// Setup tables (built once, in FP64, on the host; integer ones are exact):
+//   spectrum   Eq 2-4 (alpha, w_p, gamma), Eq 5-6 spreading
+//   buckets    log-spaced wavelength edges, w_i = geometric mean of the edge
+//              frequencies, r_i = pi g / w_i^2, c_i = g / w_i (Sec 3.2)
+//   directions 64 bins, integer weights round(Dir dtheta 2^30), codes in units
+//              of 2 pi / 10368; CDF by a wave64 scan on the GPU
+//   velocity   round(c_i dt (cos, sin) 2^32) per code, int32
+//   rates      round(eta 4 L dt w_i^3 / (pi^3 g) 2^32) per side pair (Eq "result_2")
+//   amplitude  sqrt(2 S_J(w_i) dw_i / eta) (Eq "A", importance-sampled)
+//   sources    closest-radius bucket, ring offsets / multipliers, emission
+//              cadence, crest volume = swept volume, subdivision ages
+// h0(k) and the FFT twiddles are generated on the GPU in FP64.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hwo.h"
+#include "hwo_dev.h"
+
+using namespace hwo;
+
+namespace {
+
+constexpr double kUnit = 1048576.0;
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kTwo30 = 1073741824.0;
+constexpr int kStages = 7;
+enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT };
+
+int64_t pmod(int64_t a, int64_t m) {
+  int64_t r = a % m;
+  return r < 0 ? r + m : r;
+}
+int64_t ipow3(int k) {
+  int64_t v = 1;
+  for (int i = 0; i < k; ++i) v *= 3;
+  return v;
+}
+
+struct TimedLaunch {
+  int stage;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct hwo_ocean {
+  hwo_config cfg{};
+  hwo_spectrum sp{};
+  bool have_spec = false, finalized = false;
+  std::vector<hwo_patch> patches;
+  std::vector<hwo_source> sources;
+  std::vector<int32_t> bin_cells;
+  // spectrum / buckets
+  double alpha = 0, wp = 0, gamma = 0;
+  int nb = 0, lmax = 0;
+  double w[kMaxBuckets], dw[kMaxBuckets], r[kMaxBuckets], c[kMaxBuckets];
+  int32_t margin[kMaxBuckets];
+  std::vector<uint32_t> qw;        // [nb][64]
+  std::vector<int32_t> codes;      // [64]
+  std::vector<int2> V;             // [nb][kNCode]
+  std::vector<float2> UC;          // [kNCode]
+  // scene tables
+  std::vector<PatchDev> pdev;
+  std::vector<SourceDev> sdev;
+  std::vector<float> ring_m;
+  std::vector<int2> ring_O;
+  std::vector<int32_t> src_order;
+  // device
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  Dev dev{};
+  std::vector<void *> allocs;
+  float2 *h0T = nullptr, *tw = nullptr;
+  uint32_t *cdf = nullptr, *cdfQ = nullptr;
+  int update_grid = 1024;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<TimedLaunch> tl;
+  double stage_ms[kStages] = {0};
+  int64_t stage_n[kStages] = {0};
+  int64_t n_host = 0;
+  std::string err;
+
+  int fail(int code, const std::string &m) {
+    err = m;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char *what) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return HWO_EDEVICE;
+  }
+  void *alloc(size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (cfg.dev_alloc) {
+      p = cfg.dev_alloc(bytes, cfg.alloc_ctx);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+    }
+    if (p) allocs.push_back(p);
+    return p;
+  }
+  void release_all() {
+    for (void *p : allocs) {
+      if (cfg.dev_alloc) {
+        if (cfg.dev_free) cfg.dev_free(p, cfg.alloc_ctx);
+      } else {
+        (void)hipFree(p);
+      }
+    }
+    allocs.clear();
+  }
+};
+
+#define HWO_CHECK(expr)                                   \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return o->hip_fail(e_, #expr);  \
+  } while (0)
+
+// ---------------------------------------------------------------- spectrum
+static double jonswap_h(const hwo_ocean *o, double w) {
+  if (w <= 0.0) return 0.0;
+  double sigma = (w <= o->wp) ? 0.07 : 0.09;
+  double d = w - o->wp;
+  double r = exp(-(d * d) / (2.0 * sigma * sigma * o->wp * o->wp));
+  double x = o->wp / w;
+  double x4 = x * x * x * x;
+  return o->alpha * o->cfg.g * o->cfg.g * pow(w, -5.0) * exp(-1.25 * x4) * pow(o->gamma, r);
+}
+
+static double spread_h(const hwo_ocean *o, double w) {
+  if (o->sp.spread_s >= 0.0) return o->sp.spread_s;
+  double mu = (w <= o->wp) ? 5.0 : -2.5;
+  return 16.0 * pow(w / o->wp, mu);
+}
+
+static double dir_h(double s, double theta) {
+  double norm = tgamma(s + 1.0) / (2.0 * sqrt(M_PI) * tgamma(s + 0.5));
+  double cth = cos(0.5 * theta);
+  if (cth < 0.0) cth = -cth;
+  return norm * pow(cth, 2.0 * s);
+}
+
+extern "C" {
+
+int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out) {
+  if (!cfg || !out) return HWO_EINVAL;
+  *out = nullptr;
+  const int N = cfg->fft_n;
+  if (N < 16 || N > 4096 || (N & (N - 1)) != 0) return HWO_EINVAL;
+  if (!(cfg->fft_L > 0) || !(cfg->g > 0) || !(cfg->dt > 0)) return HWO_EINVAL;
+  if (cfg->max_particles < 0 || cfg->max_particles > ((int64_t)1 << 30)) return HWO_EINVAL;
+  if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return HWO_EINVAL;
+  hwo_ocean *o = new hwo_ocean();
+  o->cfg = *cfg;
+  *out = o;
+  return HWO_OK;
+}
+
+void hwo_destroy_ocean(hwo_ocean *o) {
+  if (!o) return;
+  if (o->st) (void)hipStreamSynchronize(o->st);
+  if (o->exec) (void)hipGraphExecDestroy(o->exec);
+  if (o->graph) (void)hipGraphDestroy(o->graph);
+  for (auto &t : o->tl) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  o->release_all();
+  if (o->own_stream && o->st) (void)hipStreamDestroy(o->st);
+  delete o;
+}
+
+const char *hwo_last_error(const hwo_ocean *o) { return o ? o->err.c_str() : "null handle"; }
+
+int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
+  if (!o || !sp) return HWO_EINVAL;
+  if (o->have_spec) return o->fail(HWO_ESTATE, "spectrum already set");
+  if (!(sp->U10 > 0) || !(sp->fetch > 0)) return o->fail(HWO_EINVAL, "U10 and fetch must be positive");
+  if (sp->n_buckets < 1 || sp->n_buckets > kMaxBuckets) return o->fail(HWO_EINVAL, "n_buckets out of range");
+  if (!(sp->lambda_min > 0) || !(sp->lambda_max > sp->lambda_min)) return o->fail(HWO_EINVAL, "bad lambda range");
+  if (!(sp->eta > 0)) return o->fail(HWO_EINVAL, "eta must be positive");
+  if (sp->max_level < 0 || sp->max_level > kMaxLevel) return o->fail(HWO_EINVAL, "max_level out of range");
+  if (!(sp->subdiv_frac > 0)) return o->fail(HWO_EINVAL, "subdiv_frac must be positive");
+  if (sp->h0_mode != 0 && sp->h0_mode != 1) return o->fail(HWO_EINVAL, "h0_mode must be 0 or 1");
+  const double g = o->cfg.g, dt = o->cfg.dt;
+  const double U10 = sp->U10, fetch = sp->fetch;
+  o->sp = *sp;
+  o->nb = sp->n_buckets;
+  o->lmax = sp->max_level;
+  // Eq 4
+  o->alpha = 0.076 * pow(U10 * U10 / (fetch * g), 0.22);
+  o->wp = 22.0 * pow(g * g / (U10 * fetch), 1.0 / 3.0);
+  o->gamma = (sp->gamma > 0.0) ? sp->gamma : 7.0 * pow(g * fetch / (U10 * U10), -0.142);
+  // buckets
+  double we[kMaxBuckets + 1];
+  for (int j = 0; j <= o->nb; ++j) {
+    double le = sp->lambda_min * pow(sp->lambda_max / sp->lambda_min, (double)j / (double)o->nb);
+    we[j] = sqrt(2.0 * M_PI * g / le);
+  }
+  for (int i = 0; i < o->nb; ++i) {
+    double w = sqrt(we[i] * we[i + 1]);
+    o->w[i] = w;
+    o->dw[i] = we[i] - we[i + 1];
+    o->r[i] = M_PI * g / (w * w);
+    o->c[i] = g / w;
+    o->margin[i] = (int32_t)ceil(2.0 * o->r[i] * kUnit);
+    if (o->c[i] * dt >= 0.5) return o->fail(HWO_EINVAL, "bucket speed too high for the fixed-point step");
+    if (2.0 * o->r[i] * kUnit > 1.0e9) return o->fail(HWO_EINVAL, "bucket radius too large");
+  }
+  // direction codes and integer weights
+  const int wind_code = (int)pmod(llround(sp->wind_dir * (double)kNCode / (2.0 * M_PI)), kNCode);
+  o->codes.resize(kDirBins);
+  for (int b = 0; b < kDirBins; ++b)
+    o->codes[b] = (int32_t)pmod((int64_t)wind_code + kNCode / 2 + (int64_t)(2 * b + 1) * (kNCode / (2 * kDirBins)),
+                                kNCode);
+  o->qw.assign((size_t)o->nb * kDirBins, 0);
+  const double dth = 2.0 * M_PI / (double)kDirBins;
+  for (int i = 0; i < o->nb; ++i) {
+    double s = spread_h(o, o->w[i]);
+    int64_t tot = 0;
+    for (int b = 0; b < kDirBins; ++b) {
+      double th = -M_PI + ((double)b + 0.5) * dth;
+      int64_t qb = llround(dir_h(s, th) * dth * kTwo30);
+      o->qw[(size_t)i * kDirBins + b] = (uint32_t)qb;
+      tot += qb;
+    }
+    if (tot <= 0 || tot >= ((int64_t)1 << 32)) return o->fail(HWO_EINVAL, "degenerate direction distribution");
+  }
+  // velocity per step and unit vectors
+  o->V.resize((size_t)o->nb * kNCode);
+  o->UC.resize(kNCode);
+  for (int code = 0; code < kNCode; ++code) {
+    double ang = 2.0 * M_PI * (double)code / (double)kNCode;
+    o->UC[code] = make_float2((float)cos(ang), (float)sin(ang));
+  }
+  for (int i = 0; i < o->nb; ++i) {
+    double cdt = o->c[i] * dt;
+    for (int code = 0; code < kNCode; ++code) {
+      double ang = 2.0 * M_PI * (double)code / (double)kNCode;
+      int64_t vx = llround(cdt * cos(ang) * kTwo32);
+      int64_t vy = llround(cdt * sin(ang) * kTwo32);
+      o->V[(size_t)i * kNCode + code] = make_int2((int32_t)vx, (int32_t)vy);
+    }
+  }
+  // stream, h0, twiddles, CDF
+  if (o->cfg.stream) {
+    o->st = (hipStream_t)o->cfg.stream;
+  } else {
+    HWO_CHECK(hipStreamCreateWithFlags(&o->st, hipStreamNonBlocking));
+    o->own_stream = true;
+  }
+  const int N = o->cfg.fft_n;
+  o->h0T = (float2 *)o->alloc(sizeof(float2) * (size_t)N * N);
+  o->tw = (float2 *)o->alloc(sizeof(float2) * (size_t)N);
+  uint32_t *qd = (uint32_t *)o->alloc(sizeof(uint32_t) * o->qw.size());
+  o->cdf = (uint32_t *)o->alloc(sizeof(uint32_t) * o->qw.size());
+  o->cdfQ = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)o->nb);
+  if (!o->h0T || !o->tw || !qd || !o->cdf || !o->cdfQ) return o->fail(HWO_ENOMEM, "device allocation failed");
+  Dev d{};
+  d.N = N;
+  d.L = o->cfg.fft_L;
+  d.g = g;
+  d.nb = o->nb;
+  d.seed = o->cfg.seed;
+  launch_h0(d, o->h0T, o->tw, o->alpha, o->wp, o->gamma, sp->spread_s, sp->wind_dir, sp->h0_mode, o->st);
+  HWO_CHECK(hipGetLastError());
+  HWO_CHECK(hipMemcpyAsync(qd, o->qw.data(), sizeof(uint32_t) * o->qw.size(), hipMemcpyHostToDevice, o->st));
+  launch_cdf(d, qd, o->cdf, o->cdfQ, o->st);
+  HWO_CHECK(hipGetLastError());
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  o->have_spec = true;
+  return HWO_OK;
+}
+
+int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id) {
+  if (!o || !p) return HWO_EINVAL;
+  if (!o->have_spec) return o->fail(HWO_ESTATE, "set_spectrum first");
+  if (o->finalized) return o->fail(HWO_ESTATE, "scene is fixed after the first step");
+  if ((int)o->patches.size() >= kMaxPatches) return o->fail(HWO_ERANGE, "too many patches");
+  if (p->nx < 1 || p->ny < 1 || p->nx > 4096 || p->ny > 4096 || !(p->dx > 0))
+    return o->fail(HWO_EINVAL, "bad patch size");
+  const double dxu = p->dx * kUnit;
+  if (dxu != floor(dxu) || ((int64_t)dxu) % 2 != 0 || dxu > 1.0e8)
+    return o->fail(HWO_EINVAL, "dx must be an even multiple of 2^-20 m");
+  if ((double)p->nx * dxu > 1.5e9 || (double)p->ny * dxu > 1.5e9) return o->fail(HWO_EINVAL, "patch too large");
+  if (p->follow < -1) return o->fail(HWO_EINVAL, "bad follow id");
+  if (id) *id = (int32_t)o->patches.size();
+  o->patches.push_back(*p);
+  return HWO_OK;
+}
+
+int hwo_add_source(hwo_ocean *o, const hwo_source *s, int32_t *id) {
+  if (!o || !s) return HWO_EINVAL;
+  if (!o->have_spec) return o->fail(HWO_ESTATE, "set_spectrum first");
+  if (o->finalized) return o->fail(HWO_ESTATE, "scene is fixed after the first step");
+  if ((int)o->sources.size() >= kMaxSources) return o->fail(HWO_ERANGE, "too many sources");
+  if (s->patch < 0 || s->patch >= (int)o->patches.size()) return o->fail(HWO_EINVAL, "source patch out of range");
+  if (!(s->radius > 0) || !(s->draft >= 0)) return o->fail(HWO_EINVAL, "bad source radius/draft");
+  if (s->ring_n < 1 || s->ring_n > kMaxRing || 128 % s->ring_n != 0)
+    return o->fail(HWO_EINVAL, "ring_n must divide 128");
+  if (id) *id = (int32_t)o->sources.size();
+  o->sources.push_back(*s);
+  return HWO_OK;
+}
+
+int hwo_set_bins(hwo_ocean *o, const int32_t *bin_cells, int32_t n) {
+  if (!o || !bin_cells) return HWO_EINVAL;
+  if (!o->have_spec) return o->fail(HWO_ESTATE, "set_spectrum first");
+  if (o->finalized) return o->fail(HWO_ESTATE, "bins are fixed after the first step");
+  if (n != o->nb) return o->fail(HWO_EINVAL, "need one bin size per bucket");
+  for (int i = 0; i < n; ++i)
+    if (bin_cells[i] < 1 || bin_cells[i] > 4096) return o->fail(HWO_EINVAL, "bin size out of range");
+  o->bin_cells.assign(bin_cells, bin_cells + n);
+  return HWO_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- finalize
+static int build_scene_tables(hwo_ocean *o) {
+  const double g = o->cfg.g, dt = o->cfg.dt;
+  const int np = (int)o->patches.size(), ns = (int)o->sources.size(), nb = o->nb;
+  if (o->bin_cells.empty()) o->bin_cells.assign(nb, 16);
+  for (int p = 0; p < np; ++p)
+    if (o->patches[p].follow >= ns) return o->fail(HWO_EINVAL, "patch follows a missing source");
+  // sources sorted by patch (stable)
+  o->src_order.resize(ns);
+  for (int s = 0; s < ns; ++s) o->src_order[s] = s;
+  std::stable_sort(o->src_order.begin(), o->src_order.end(),
+                   [&](int a, int b) { return o->sources[a].patch < o->sources[b].patch; });
+  o->pdev.assign(np, PatchDev{});
+  int64_t bins = 0, tiles = 0, cells = 0;
+  const double dxf = o->cfg.fft_L / (double)o->cfg.fft_n;
+  for (int p = 0; p < np; ++p) {
+    const hwo_patch &hp = o->patches[p];
+    PatchDev &P = o->pdev[p];
+    P.ax = hp.anchor_x;
+    P.ay = hp.anchor_y;
+    P.dx = hp.dx;
+    P.nx = hp.nx;
+    P.ny = hp.ny;
+    P.dxu = (int32_t)(hp.dx * kUnit);
+    P.follow = hp.follow;
+    const double eta = (hp.eta > 0.0) ? hp.eta : o->sp.eta;
+    const double rmax = o->r[nb - 1];
+    const double lmin = (double)(hp.nx < hp.ny ? hp.nx : hp.ny) * hp.dx / 4.0;
+    P.band = (float)((hp.blend_band > 0.0) ? hp.blend_band : (rmax < lmin ? rmax : lmin));
+    P.ratio = (float)(hp.dx / dxf);
+    const double Lx = (double)hp.nx * hp.dx, Ly = (double)hp.ny * hp.dx;
+    P.bin_lo = (int32_t)bins;
+    for (int i = 0; i < nb; ++i) {
+      const double w = o->w[i];
+      P.A[i] = (float)sqrt(2.0 * jonswap_h(o, w) * o->dw[i] / eta);
+      const double gx = 4.0 * Ly * dt * w * w * w / (M_PI * M_PI * M_PI * g);
+      const double gy = 4.0 * Lx * dt * w * w * w / (M_PI * M_PI * M_PI * g);
+      P.Rx[i] = (uint64_t)llround(eta * gx * kTwo32);
+      P.Ry[i] = (uint64_t)llround(eta * gy * kTwo32);
+      if (P.Rx[i] > ((uint64_t)1 << 52) || P.Ry[i] > ((uint64_t)1 << 52))
+        return o->fail(HWO_EINVAL, "injection rate too high");
+      const int64_t binu = (int64_t)o->bin_cells[i] * P.dxu;
+      if (binu >= ((int64_t)1 << 31)) return o->fail(HWO_EINVAL, "bin too large");
+      P.binu[i] = (int32_t)binu;
+      const int64_t m = o->margin[i];
+      P.nbx[i] = (int32_t)(floor_div((int64_t)hp.nx * P.dxu + 2 * m, binu) + 1);
+      P.nby[i] = (int32_t)(floor_div((int64_t)hp.ny * P.dxu + 2 * m, binu) + 1);
+      P.binbase[i] = (int32_t)bins;
+      bins += (int64_t)P.nbx[i] * P.nby[i];
+      if (bins > ((int64_t)1 << 28)) return o->fail(HWO_EINVAL, "too many bins");
+    }
+    P.bin_hi = (int32_t)bins;
+    P.ntx = (hp.nx + kTile - 1) / kTile;
+    P.nty = (hp.ny + kTile - 1) / kTile;
+    P.tile0 = (int32_t)tiles;
+    tiles += (int64_t)P.ntx * P.nty;
+    P.cell0 = cells;
+    cells += (int64_t)hp.nx * hp.ny;
+  }
+  // source ranges per patch in sorted order
+  for (int p = 0; p < np; ++p) {
+    int lo = 0;
+    while (lo < ns && o->sources[o->src_order[lo]].patch < p) ++lo;
+    int hi = lo;
+    while (hi < ns && o->sources[o->src_order[hi]].patch == p) ++hi;
+    o->pdev[p].src_lo = lo;
+    o->pdev[p].src_hi = hi;
+  }
+  o->sdev.assign(ns, SourceDev{});
+  o->ring_m.clear();
+  o->ring_O.clear();
+  for (int si = 0; si < ns; ++si) {
+    const hwo_source &hs = o->sources[si];
+    SourceDev &S = o->sdev[si];
+    S.x0 = hs.x0;
+    S.y0 = hs.y0;
+    S.vx = hs.vx;
+    S.vy = hs.vy;
+    S.patch = hs.patch;
+    S.ne = hs.ring_n;
+    S.a0 = kNCode / hs.ring_n;
+    S.ring0 = (int32_t)o->ring_m.size();
+    const double R = hs.radius;
+    const double speed = sqrt(hs.vx * hs.vx + hs.vy * hs.vy);
+    const double heading = atan2(hs.vy, hs.vx);
+    int best = 0;
+    for (int i = 1; i < nb; ++i)
+      if (fabs(o->r[i] - R) < fabs(o->r[best] - R)) best = i;
+    S.bucket = best;
+    const double rb = o->r[best], cb = o->c[best];
+    double sum_abs = 0.0;
+    for (int j = 0; j < hs.ring_n; ++j) {
+      const double phi = 2.0 * M_PI * (double)j / (double)hs.ring_n;
+      const double m = cos(phi - heading);
+      sum_abs += fabs(m);
+      o->ring_m.push_back((float)m);
+      const int64_t ox = llround(R * cos(phi) * kUnit), oy = llround(R * sin(phi) * kUnit);
+      o->ring_O.push_back(make_int2((int32_t)ox, (int32_t)oy));
+    }
+    if (speed > 0.0) {
+      const double e = floor(0.5 * rb / (speed * dt));
+      const int64_t E = e < 1.0 ? 1 : (int64_t)e;
+      S.E = (int32_t)std::min<int64_t>(E, 1 << 30);
+      S.B = (float)(2.0 * R * speed * (double)E * dt * hs.draft / (rb * rb * sum_abs));
+    } else {
+      S.E = 0;
+      S.B = 0.f;
+    }
+    for (int L = 0; L < kMaxLevel; ++L) {
+      const double alpha = 2.0 * M_PI / ((double)hs.ring_n * (double)ipow3(L));
+      const double x = (o->sp.subdiv_frac * rb / alpha - R) / (cb * dt);
+      int64_t T = (int64_t)floor(x) + 1;
+      if (T < 0) T = 0;
+      S.T[L] = (int32_t)std::min<int64_t>(T, (int64_t)1 << 30);
+    }
+  }
+  o->dev.nbins = (int32_t)bins;
+  o->dev.ntiles = (int32_t)tiles;
+  // particle capacity
+  int64_t cap = o->cfg.max_particles;
+  if (cap == 0) {
+    double est = 0.0;
+    for (int p = 0; p < np; ++p) {
+      const hwo_patch &hp = o->patches[p];
+      const double span = (double)std::max(hp.nx, hp.ny) * hp.dx;
+      for (int i = 0; i < nb; ++i) {
+        const double rate = (double)(o->pdev[p].Rx[i] + o->pdev[p].Ry[i]) / kTwo32;
+        const double steps = std::min((1.5 * span + 4.0 * o->r[i]) / (o->c[i] * dt), 4096.0);
+        est += rate * steps;
+      }
+    }
+    for (int si = 0; si < ns; ++si) {
+      const SourceDev &S = o->sdev[si];
+      if (S.E <= 0) continue;
+      const hwo_patch &hp = o->patches[S.patch];
+      const double span = (double)std::max(hp.nx, hp.ny) * hp.dx;
+      const double steps = std::min((span + 4.0 * o->r[S.bucket]) / (o->c[S.bucket] * dt), 4096.0);
+      est += (double)S.ne * ipow3(o->lmax) * (steps / S.E + 1.0);
+    }
+    cap = (int64_t)(1.5 * est) + 65536;
+    cap = std::min<int64_t>(cap, (int64_t)1 << 30);
+  }
+  o->dev.cap = (int32_t)cap;
+  (void)cells;
+  return HWO_OK;
+}
+
+template <class T>
+static T *upload(hwo_ocean *o, const std::vector<T> &v, int *rc) {
+  T *p = (T *)o->alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+  if (!p) {
+    *rc = o->fail(HWO_ENOMEM, "device allocation failed");
+    return nullptr;
+  }
+  if (!v.empty()) {
+    hipError_t e = hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, o->st);
+    if (e != hipSuccess) *rc = o->hip_fail(e, "upload");
+  }
+  return p;
+}
+
+static int finalize(hwo_ocean *o) {
+  if (o->finalized) return HWO_OK;
+  if (!o->have_spec) return o->fail(HWO_ESTATE, "set_spectrum first");
+  int rc = build_scene_tables(o);
+  if (rc) return rc;
+  Dev &d = o->dev;
+  const int np = (int)o->patches.size(), ns = (int)o->sources.size(), nb = o->nb, N = o->cfg.fft_n;
+  d.np = np;
+  d.ns = ns;
+  d.nb = nb;
+  d.N = N;
+  d.compact = o->cfg.compact ? 1 : 0;
+  d.lmax = o->lmax;
+  d.n_inj_slots = np * nb * 2;
+  d.g = o->cfg.g;
+  d.dt = o->cfg.dt;
+  d.L = o->cfg.fft_L;
+  d.dxf = o->cfg.fft_L / (double)N;
+  d.seed = o->cfg.seed;
+  rc = HWO_OK;
+  d.patches = upload(o, o->pdev, &rc);
+  d.sources = upload(o, o->sdev, &rc);
+  d.src_order = upload(o, o->src_order, &rc);
+  d.V = upload(o, o->V, &rc);
+  d.UC = upload(o, o->UC, &rc);
+  d.cdf = o->cdf;
+  d.cdfQ = o->cdfQ;
+  d.codes = upload(o, o->codes, &rc);
+  std::vector<float> br(nb);
+  std::vector<int32_t> bm(nb);
+  for (int i = 0; i < nb; ++i) {
+    br[i] = (float)o->r[i];
+    bm[i] = o->margin[i];
+  }
+  d.bucket_r = upload(o, br, &rc);
+  d.margin = upload(o, bm, &rc);
+  d.ring_m = upload(o, o->ring_m, &rc);
+  d.ring_O = upload(o, o->ring_O, &rc);
+  if (rc) return rc;
+  int64_t cells = 0;
+  for (auto &hp : o->patches) cells += (int64_t)hp.nx * hp.ny;
+  const size_t rec = d.compact ? sizeof(RecCompact) : sizeof(RecWide);
+  d.glob = (Globals *)o->alloc(sizeof(Globals));
+  d.sp = (StepPatch *)o->alloc(sizeof(StepPatch) * std::max(np, 1));
+  d.inj_off = (int32_t *)o->alloc(sizeof(int32_t) * (d.n_inj_slots + 1));
+  d.em_off = (int32_t *)o->alloc(sizeof(int32_t) * (ns + 1));
+  d.src_pos = (int2 *)o->alloc(sizeof(int2) * std::max(ns, 1));
+  d.ctr = (unsigned long long *)o->alloc(sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1));
+  d.hist = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.nbins + 1));
+  d.off = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.nbins + 1));
+  d.cur = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.nbins + 1));
+  d.bsum = (int32_t *)o->alloc(sizeof(int32_t) * (size_t)std::max(scan_blocks(d.nbins), 1));
+  d.S0 = o->alloc(rec * (size_t)d.cap);
+  d.S1 = o->alloc(rec * (size_t)d.cap);
+  d.h0T = o->h0T;
+  d.tw = o->tw;
+  d.FT = (float2 *)o->alloc(sizeof(float2) * (size_t)(N / 2 + 1) * N);
+  d.H = (float *)o->alloc(sizeof(float) * (size_t)N * N);
+  d.raw = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
+  d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
+  if (!d.glob || !d.sp || !d.inj_off || !d.em_off || !d.src_pos || !d.ctr || !d.hist || !d.off || !d.cur ||
+      !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
+    return o->fail(HWO_ENOMEM, "device allocation failed");
+  HWO_CHECK(hipMemsetAsync(d.glob, 0, sizeof(Globals), o->st));
+  HWO_CHECK(hipMemsetAsync(d.ctr, 0, sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.hist, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.off, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.cur, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.raw, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.blend, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.H, 0, sizeof(float) * (size_t)N * N, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  int dev_id = 0, cus = 256;
+  (void)hipGetDevice(&dev_id);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
+  o->update_grid = std::max(64, 4 * cus);
+  o->finalized = true;
+  return HWO_OK;
+}
+
+// ---------------------------------------------------------------- stepping
+static void timed(hwo_ocean *o, int stage, void (*fn)(hwo_ocean *, void *), void *arg) {
+  if (!o->timing) {
+    fn(o, arg);
+    return;
+  }
+  TimedLaunch t;
+  t.stage = stage;
+  (void)hipEventCreate(&t.a);
+  (void)hipEventCreate(&t.b);
+  (void)hipEventRecord(t.a, o->st);
+  fn(o, arg);
+  (void)hipEventRecord(t.b, o->st);
+  o->tl.push_back(t);
+}
+
+struct PatchArg {
+  int p0, p1;
+  int b0, b1;
+  bool first, last;
+};
+
+static void run_step(hwo_ocean *o) {
+  Dev &d = o->dev;
+  hipStream_t st = o->st;
+  timed(o, ST_PARAMS, [](hwo_ocean *oo, void *) { launch_params(oo->dev, oo->st); }, nullptr);
+  timed(o, ST_FFT_A, [](hwo_ocean *oo, void *) { launch_fft_a(oo->dev, oo->st); }, nullptr);
+  timed(o, ST_FFT_B, [](hwo_ocean *oo, void *) { launch_fft_b(oo->dev, oo->st); }, nullptr);
+  if (d.np == 0) return;
+  std::vector<PatchArg> groups;
+  if (o->cfg.batched) {
+    groups.push_back({0, d.np, 0, d.nbins, true, true});
+  } else {
+    for (int p = 0; p < d.np; ++p)
+      groups.push_back({p, p + 1, o->pdev[p].bin_lo, o->pdev[p].bin_hi, p == 0, p == d.np - 1});
+  }
+  for (auto &gp : groups) {
+    timed(o, ST_COUNT, [](hwo_ocean *oo, void *a) {
+      auto *g = (PatchArg *)a;
+      launch_update(oo->dev, g->p0, g->p1, false, oo->update_grid, oo->st);
+    }, &gp);
+    timed(o, ST_SCAN, [](hwo_ocean *oo, void *a) {
+      auto *g = (PatchArg *)a;
+      launch_scan(oo->dev, g->b0, g->b1, g->first, g->last, oo->st);
+    }, &gp);
+    timed(o, ST_SCATTER, [](hwo_ocean *oo, void *a) {
+      auto *g = (PatchArg *)a;
+      launch_update(oo->dev, g->p0, g->p1, true, oo->update_grid, oo->st);
+    }, &gp);
+  }
+  for (auto &gp : groups) {
+    timed(o, ST_SPLAT, [](hwo_ocean *oo, void *a) {
+      auto *g = (PatchArg *)a;
+      const PatchDev &P0 = oo->pdev[g->p0];
+      const PatchDev &P1 = oo->pdev[g->p1 - 1];
+      const int t0 = P0.tile0, t1 = P1.tile0 + P1.ntx * P1.nty;
+      launch_splat_tiles(oo->dev, t0, t1 - t0, oo->st);
+    }, &gp);
+  }
+  (void)st;
+}
+
+static int collect_timing(hwo_ocean *o) {
+  if (o->tl.empty()) return HWO_OK;
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  for (auto &t : o->tl) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t.a, t.b);
+    o->stage_ms[t.stage] += ms;
+    o->stage_n[t.stage] += 1;
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  o->tl.clear();
+  return HWO_OK;
+}
+
+extern "C" {
+
+int hwo_step(hwo_ocean *o, int32_t nsteps) {
+  if (!o) return HWO_EINVAL;
+  if (nsteps < 0) return o->fail(HWO_EINVAL, "nsteps must be >= 0");
+  int rc = finalize(o);
+  if (rc) return rc;
+  if (o->n_host + nsteps > ((int64_t)1 << 31) - 1) return o->fail(HWO_ERANGE, "step index overflow");
+  const bool use_graph = o->cfg.batched && !o->timing;
+  for (int32_t k = 0; k < nsteps; ++k) {
+    if (use_graph) {
+      if (!o->exec) {
+        HWO_CHECK(hipStreamBeginCapture(o->st, hipStreamCaptureModeThreadLocal));
+        run_step(o);
+        HWO_CHECK(hipStreamEndCapture(o->st, &o->graph));
+        HWO_CHECK(hipGraphInstantiate(&o->exec, o->graph, nullptr, nullptr, 0));
+      }
+      HWO_CHECK(hipGraphLaunch(o->exec, o->st));
+    } else {
+      run_step(o);
+      HWO_CHECK(hipGetLastError());
+    }
+    o->n_host += 1;
+    if (o->timing && o->tl.size() > 4096) {
+      rc = collect_timing(o);
+      if (rc) return rc;
+    }
+  }
+  return HWO_OK;
+}
+
+int hwo_sync(hwo_ocean *o) {
+  if (!o) return HWO_EINVAL;
+  if (o->st) HWO_CHECK(hipStreamSynchronize(o->st));
+  return HWO_OK;
+}
+
+int64_t hwo_step_index(const hwo_ocean *o) { return o ? o->n_host : -1; }
+
+int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst, int64_t dst_elems,
+                        int32_t dst_is_device) {
+  if (!o || !dst) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  const Dev &d = o->dev;
+  const float *src;
+  int64_t n;
+  if (which == -1) {
+    src = d.H;
+    n = (int64_t)d.N * d.N;
+  } else {
+    if (which < 0 || which >= d.np) return o->fail(HWO_ERANGE, "patch out of range");
+    if (layer != 0 && layer != 1) return o->fail(HWO_EINVAL, "layer must be 0 or 1");
+    const PatchDev &P = o->pdev[which];
+    src = (layer == 0 ? d.blend : d.raw) + P.cell0;
+    n = (int64_t)P.nx * P.ny;
+  }
+  if (dst_elems < n) return o->fail(HWO_ERANGE, "destination too small");
+  HWO_CHECK(hipMemcpyAsync(dst, src, sizeof(float) * (size_t)n,
+                           dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  return HWO_OK;
+}
+
+int hwo_read_counts(hwo_ocean *o, int32_t patch, int64_t *dst, int64_t dst_elems) {
+  if (!o || !dst) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  const Dev &d = o->dev;
+  if (patch < 0 || patch >= d.np) return o->fail(HWO_ERANGE, "patch out of range");
+  if (dst_elems < 6 * (int64_t)d.nb) return o->fail(HWO_ERANGE, "destination too small");
+  const PatchDev &P = o->pdev[patch];
+  std::vector<unsigned long long> ctr((size_t)d.nb * CNT_NUM);
+  std::vector<int32_t> off((size_t)(P.bin_hi - P.bin_lo) + 1);
+  Globals g{};
+  HWO_CHECK(hipMemcpyAsync(ctr.data(), d.ctr + (size_t)patch * d.nb * CNT_NUM, sizeof(unsigned long long) * ctr.size(),
+                           hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipMemcpyAsync(off.data(), d.off + P.bin_lo, sizeof(int32_t) * off.size(), hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipMemcpyAsync(&g, d.glob, sizeof(Globals), hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  const bool stepped = o->n_host > 0;
+  for (int b = 0; b < d.nb; ++b) {
+    const int lo = P.binbase[b] - P.bin_lo, hi = lo + P.nbx[b] * P.nby[b];
+    dst[6 * b + 0] = stepped ? (int64_t)off[hi] - off[lo] : 0;
+    dst[6 * b + 1] = (int64_t)ctr[(size_t)b * CNT_NUM + CNT_INJ];
+    dst[6 * b + 2] = (int64_t)ctr[(size_t)b * CNT_NUM + CNT_EMIT];
+    dst[6 * b + 3] = (int64_t)ctr[(size_t)b * CNT_NUM + CNT_SUB];
+    dst[6 * b + 4] = (int64_t)ctr[(size_t)b * CNT_NUM + CNT_DIED];
+    dst[6 * b + 5] = (int64_t)g.dropped;
+  }
+  if (g.err) return o->fail(HWO_ERANGE, "a window left the fixed-point position range");
+  if (g.dropped) return o->fail(HWO_EOVERFLOW, "particle capacity exceeded");
+  return HWO_OK;
+}
+
+int hwo_tile_dims(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dims) {
+  if (!o || !dims) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  if (patch < 0 || patch >= o->dev.np || bucket < 0 || bucket >= o->nb) return o->fail(HWO_ERANGE, "out of range");
+  const PatchDev &P = o->pdev[patch];
+  dims[0] = o->bin_cells[bucket];
+  dims[1] = P.nbx[bucket];
+  dims[2] = P.nby[bucket];
+  return HWO_OK;
+}
+
+int hwo_read_tiles(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dst, int64_t n) {
+  if (!o || !dst) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  if (patch < 0 || patch >= o->dev.np || bucket < 0 || bucket >= o->nb) return o->fail(HWO_ERANGE, "out of range");
+  const PatchDev &P = o->pdev[patch];
+  const int64_t nh = (int64_t)P.nbx[bucket] * P.nby[bucket];
+  if (n < nh) return o->fail(HWO_ERANGE, "destination too small");
+  std::vector<int32_t> off((size_t)nh + 1);
+  HWO_CHECK(hipMemcpyAsync(off.data(), o->dev.off + P.binbase[bucket], sizeof(int32_t) * off.size(),
+                           hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  for (int64_t k = 0; k < nh; ++k) dst[k] = o->n_host > 0 ? (int64_t)off[k + 1] - off[k] : 0;
+  return HWO_OK;
+}
+
+int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_out) {
+  if (!o || !n_out) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  const Dev &d = o->dev;
+  Globals g{};
+  HWO_CHECK(hipMemcpyAsync(&g, d.glob, sizeof(Globals), hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  const int64_t n = o->n_host > 0 ? g.n_live : 0;
+  *n_out = n;
+  if (!dst) return HWO_OK;
+  if (max_recs < n) return o->fail(HWO_ERANGE, "destination too small");
+  const void *S = (g.n & 1) ? d.S1 : d.S0;
+  const int64_t step = g.n;
+  if (d.compact) {
+    std::vector<RecCompact> h((size_t)n);
+    if (n) HWO_CHECK(hipMemcpy(h.data(), S, sizeof(RecCompact) * n, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < n; ++k) {
+      const RecCompact &r = h[k];
+      const uint32_t m = r.meta;
+      const int64_t age = (int64_t)(((uint32_t)step - (r.bc & 0xFFFFu)) & 0xFFFFu);
+      int64_t *q = dst + 10 * k;
+      q[0] = m_patch(m); q[1] = m_bucket(m); q[2] = m_kind(m); q[3] = m_level(m);
+      q[4] = r.bc >> 16; q[5] = step - age; q[6] = r.ox; q[7] = r.oy;
+      q[8] = m_src(m) == kNoSource ? -1 : (int64_t)m_src(m); q[9] = m_slot(m);
+    }
+  } else {
+    std::vector<RecWide> h((size_t)n);
+    if (n) HWO_CHECK(hipMemcpy(h.data(), S, sizeof(RecWide) * n, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < n; ++k) {
+      const RecWide &r = h[k];
+      const uint32_t m = r.meta;
+      int64_t *q = dst + 10 * k;
+      q[0] = m_patch(m); q[1] = m_bucket(m); q[2] = m_kind(m); q[3] = m_level(m);
+      q[4] = r.code; q[5] = r.birth; q[6] = r.ox; q[7] = r.oy;
+      q[8] = m_src(m) == kNoSource ? -1 : (int64_t)m_src(m); q[9] = m_slot(m);
+    }
+  }
+  return HWO_OK;
+}
+
+int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, float *dst, int64_t dst_elems) {
+  if (!o || (!recs && n > 0) || !dst || n < 0 || n > (1 << 24)) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  const Dev &d = o->dev;
+  if (patch < 0 || patch >= d.np) return o->fail(HWO_ERANGE, "patch out of range");
+  const PatchDev &P = o->pdev[patch];
+  const int64_t cells = (int64_t)P.nx * P.ny;
+  if (dst_elems < cells) return o->fail(HWO_ERANGE, "destination too small");
+  // the window of the current step is needed; make sure sp[] is filled
+  if (o->n_host == 0) return o->fail(HWO_ESTATE, "step at least once before splatting");
+  const int64_t step = o->n_host;
+  std::vector<uint8_t> host;
+  const size_t rs = d.compact ? sizeof(RecCompact) : sizeof(RecWide);
+  host.resize(rs * (size_t)std::max<int64_t>(n, 1));
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t *q = recs + 10 * k;
+    if (q[0] != patch || q[1] < 0 || q[1] >= o->nb || q[4] < 0 || q[4] >= kNCode || q[3] < 0 || q[3] > kMaxLevel ||
+        q[5] > step || step - q[5] > kAgeMax)
+      return o->fail(HWO_EINVAL, "bad particle record");
+    if (q[2] == 1 && (q[8] < 0 || q[8] >= d.ns || q[9] < 0 || q[9] >= o->sdev[q[8]].ne))
+      return o->fail(HWO_EINVAL, "bad ring particle record");
+    const uint32_t src = q[2] == 1 ? (uint32_t)q[8] : kNoSource;
+    const uint32_t meta = pack_meta((uint32_t)q[3], (uint32_t)q[2], (uint32_t)q[1], (uint32_t)q[0], src,
+                                    q[2] == 1 ? (uint32_t)q[9] : 0u);
+    if (d.compact) {
+      RecCompact r;
+      r.ox = (int32_t)q[6]; r.oy = (int32_t)q[7];
+      r.bc = ((uint32_t)q[5] & 0xFFFFu) | ((uint32_t)q[4] << 16);
+      r.meta = meta;
+      memcpy(host.data() + rs * k, &r, rs);
+    } else {
+      RecWide r;
+      r.ox = (int32_t)q[6]; r.oy = (int32_t)q[7]; r.birth = (int32_t)q[5]; r.code = (int32_t)q[4];
+      r.meta = meta;
+      float amp;
+      if (q[2] == 0) amp = P.A[q[1]];
+      else {
+        const SourceDev &S = o->sdev[q[8]];
+        amp = S.B * o->ring_m[S.ring0 + q[9]];
+        for (int l = 0; l < q[3]; ++l) amp *= (1.0f / 3.0f);
+      }
+      r.amp = amp; r.pad0 = 0; r.pad1 = 0;
+      memcpy(host.data() + rs * k, &r, rs);
+    }
+  }
+  void *drec = nullptr;
+  float *dout = nullptr;
+  HWO_CHECK(hipMalloc(&drec, host.size()));
+  HWO_CHECK(hipMalloc((void **)&dout, sizeof(float) * (size_t)cells));
+  hipError_t e = hipMemcpyAsync(drec, host.data(), host.size(), hipMemcpyHostToDevice, o->st);
+  if (e == hipSuccess) {
+    launch_splat_direct(d, P.tile0, P.ntx * P.nty, drec, (int)n, dout, P.cell0, o->st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(dst, dout, sizeof(float) * (size_t)cells, hipMemcpyDeviceToHost, o->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(o->st);
+  (void)hipFree(drec);
+  (void)hipFree(dout);
+  if (e != hipSuccess) return o->hip_fail(e, "test_splat");
+  return HWO_OK;
+}
+
+int hwo_set_timing(hwo_ocean *o, int32_t enable) {
+  if (!o) return HWO_EINVAL;
+  int rc = collect_timing(o);
+  if (rc) return rc;
+  o->timing = enable != 0;
+  for (int s = 0; s < kStages; ++s) {
+    o->stage_ms[s] = 0.0;
+    o->stage_n[s] = 0;
+  }
+  return HWO_OK;
+}
+
+int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n) {
+  if (!o || !ms || !launches || n < kStages) return HWO_EINVAL;
+  int rc = collect_timing(o);
+  if (rc) return rc;
+  for (int s = 0; s < kStages; ++s) {
+    ms[s] = o->stage_ms[s];
+    launches[s] = o->stage_n[s];
+  }
+  return HWO_OK;
+}
+
+int32_t hwo_record_bytes(const hwo_ocean *o) {
+  if (!o) return 0;
+  return o->cfg.compact ? (int32_t)sizeof(RecCompact) : (int32_t)sizeof(RecWide);
+}
+
+}  // extern "C"

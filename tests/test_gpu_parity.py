@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Integer state (per-bucket counts, per-bin histograms and the multiset of
+particle records) must be bit-exact; heights within 1e-4 relative RMS,
+reported separately for the background, the raw wave-particle map and the
+blended map.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2511_02852_amd import scenes
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2511_02852_amd import hwo
+    hwo.lib()
+    yield
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_rms(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.sqrt(np.mean((a - b) ** 2)) / max(np.sqrt(np.mean(b ** 2)), 1e-300))
+
+
+def canon(P):
+    if P.shape[0] == 0:
+        return P
+    return P[np.lexsort(P.T[::-1])]
+
+
+def check_integer_state(g, o, scene):
+    for p in range(len(scene.patches)):
+        gc = g.counts(p)
+        oc = o.counts(p)
+        assert np.array_equal(gc[:, :5], oc), f"patch {p} counts\n{gc}\n{oc}"
+        assert np.all(gc[:, 5] == 0)
+        for b in range(o.nb):
+            assert g.tile_dims(p, b) == o.tile_dims(p, b)
+            assert np.array_equal(g.tiles(p, b), o.tiles(p, b)), f"patch {p} bucket {b} tiles"
+    gp, op = canon(g.particles()), canon(o.particles())
+    assert gp.shape == op.shape, (gp.shape, op.shape)
+    assert np.array_equal(gp, op), "particle multisets differ"
+
+
+def check_heights(g, o, scene, patches=None, tol=TOL):
+    H = o.background()
+    e_bg = rel_rms(g.background(), H)
+    out = {"bg": e_bg}
+    assert e_bg <= tol, f"background rel rms {e_bg}"
+    for p in (range(len(scene.patches)) if patches is None else patches):
+        raw, bl = o.patch_maps(p, H)
+        e_raw = rel_rms(g.patch_map(p, 1), raw)
+        e_bl = rel_rms(g.patch_map(p, 0), bl)
+        out[p] = (e_raw, e_bl)
+        assert e_raw <= tol, f"patch {p} raw rel rms {e_raw}"
+        assert e_bl <= tol, f"patch {p} blended rel rms {e_bl}"
+    return out
+
+
+def make(scene, **kw):
+    from paper_2511_02852_amd import hwo
+    return hwo.Ocean(scene, **kw), oracle.Oracle(scene)
+
+
+# ---------------------------------------------------------------- background
+@pytest.mark.parametrize("N,L", [(16, 64.0), (64, 256.0), (256, 500.0), (512, 1000.0), (1024, 2000.0),
+                                 (2048, 4000.0), (4096, 8000.0)])
+def test_background_matches_oracle(N, L):
+    s = scenes.Scene(name="bg", fft_n=N, fft_L=L, seed=5, spectrum=scenes.Spectrum(U10=15.0))
+    say(f"background N={N}")
+    g, o = make(s, torch_memory=True)
+    for steps in (1, 36):
+        g.step(steps)
+        o.step(steps)
+        e = rel_rms(g.background(), o.background())
+        say(f"  n={o.n} rel_rms={e:.3e}")
+        assert e <= TOL
+
+
+def test_background_unit_modulus_and_mitsuyasu():
+    sp = scenes.Spectrum(U10=7.0, fetch=30e3, gamma=-1.0, spread_s=-1.0, h0_mode=1, wind_dir=0.6)
+    s = scenes.Scene(name="bg2", fft_n=256, fft_L=300.0, seed=9, spectrum=sp)
+    g, o = make(s)
+    g.step(17)
+    o.step(17)
+    assert rel_rms(g.background(), o.background()) <= TOL
+
+
+# ---------------------------------------------------------------- c1
+def test_c1_every_step():
+    s = scenes.c1()
+    g, o = make(s)
+    for n in range(1, s.steps + 1):
+        g.step(1)
+        o.step(1)
+        check_integer_state(g, o, s)
+        e = check_heights(g, o, s)
+        say(f"c1 n={n} live={int(g.counts(0)[:, 0].sum())} err={e}")
+
+
+# ---------------------------------------------------------------- c2 forms
+@pytest.mark.parametrize("form", ["plain", "compact", "batched"])
+def test_c2_forms(form):
+    s = scenes.c2()
+    kw = dict(plain=dict(compact=False, batched=False), compact=dict(compact=True, batched=False),
+              batched=dict(compact=True, batched=True))[form]
+    g, o = make(s, **kw)
+    done = 0
+    for target in (60, 300, 600):
+        g.step(target - done)
+        o.step(target - done)
+        done = target
+        say(f"c2 {form} n={target}")
+        check_integer_state(g, o, s)
+        if target in (60, 600):
+            e = check_heights(g, o, s)
+            say(f"  live={int(g.counts(0)[:, 0].sum())} err={e}")
+
+
+def test_c2_subdivision_happens():
+    s = scenes.c2()
+    g, o = make(s, compact=True)
+    g.step(330)
+    o.step(330)
+    c = g.counts(0)
+    assert c[:, 3].sum() > 0
+    check_integer_state(g, o, s)
+
+
+# ---------------------------------------------------------------- large scenes, short runs
+@pytest.mark.parametrize("name,steps", [("c3", 12), ("c5", 6)])
+def test_batched_scenes_short(name, steps):
+    s = scenes.get(name)
+    say(f"{name}: {len(s.patches)} patches, {steps} steps")
+    g, o = make(s)
+    g.step(steps)
+    o.step(steps)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s, patches=[0, 1, len(s.patches) - 1])
+    say(f"  err={e}")
+
+
+def test_c4_far_anchor():
+    s = scenes.c4()
+    g, o = make(s)
+    g.step(90)
+    o.step(90)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s)
+    say(f"c4 err={e}")
+
+
+# ---------------------------------------------------------------- splat pins on the GPU
+def pin_scene():
+    sp = scenes.Spectrum(U10=10.0, n_buckets=1, lambda_min=1.0, lambda_max=4.0, eta=4.0)
+    return scenes.Scene(name="pin", fft_n=64, fft_L=256.0, seed=3, spectrum=sp,
+                        patches=[scenes.Patch(anchor_x=0.0, anchor_y=0.0, nx=96, ny=80, dx=0.25)],
+                        bins=[8])
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_gpu_pair_lattice_cosine(compact):
+    """Particles at spacing lambda along +x and r across sum to A cos(k(x - x0))."""
+    from paper_2511_02852_amd import hwo
+    s = pin_scene()
+    g = hwo.Ocean(s, compact=compact)
+    o = oracle.Oracle(s)
+    g.step(1)
+    r, lam = o.bucket(0)["r"], o.bucket(0)["lam"]
+    A = o.patch_bucket(0, 0)["A"]
+    x0 = 3.3
+    recs = []
+    for m in range(-3, 16):
+        for k in range(-3, 28):
+            recs.append([0, 0, 0, 0, 0, 1, int(round((x0 + m * lam) * 2 ** 20)), int(round((0.1 + k * r) * 2 ** 20)),
+                         -1, 0])
+    h = g.test_splat(0, np.array(recs))
+    p = s.patches[0]
+    X = (np.arange(p.nx) + 0.5) * p.dx
+    want = A * np.cos(np.pi * (X - round(x0 * 2 ** 20) / 2 ** 20) / r)
+    err = np.max(np.abs(h - want[None, :]))
+    assert err <= 2e-5 * A, err
+
+
+@pytest.mark.parametrize("compact", [False, True])
+def test_gpu_splat_random_particles(compact):
+    """Hand-placed boundary and ring particles of every bucket, c2 geometry."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.c2()
+    g = hwo.Ocean(s, compact=compact)
+    o = oracle.Oracle(s)
+    g.step(1)
+    o.step(1)
+    wx, wy = o.window(0)
+    rng = np.random.default_rng(4)
+    dxu = int(0.25 * 2 ** 20)
+    recs = []
+    for k in range(3000):
+        b = int(rng.integers(0, 8))
+        kind = int(rng.random() < 0.3)
+        si = o.source_info(0)
+        if kind:
+            b = si["bucket"]
+        level = int(rng.integers(0, 3)) if kind else 0
+        x = int((wx + rng.uniform(-10, 266)) * dxu)
+        y = int((wy + rng.uniform(-10, 266)) * dxu)
+        code = int(rng.integers(0, 10368))
+        birth = int(rng.integers(0, 2))
+        recs.append([0, b, kind, level, code, birth, x, y, 0 if kind else -1, int(rng.integers(0, 64)) if kind else 0])
+    recs = np.array(recs)
+    h = g.test_splat(0, recs)
+    ref = o.splat(0, recs)
+    e = rel_rms(h, ref)
+    say(f"splat random rel rms {e:.2e}")
+    assert e <= 1e-5
+
+
+# ---------------------------------------------------------------- edge cases
+def test_capacity_overflow_reported():
+    """More live particles than capacity: records beyond it are dropped,
+    the drop is counted and reported, nothing is written out of bounds."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.c1()
+    g = hwo.Ocean(s, max_particles=500)
+    g.step(16)
+    with pytest.raises(hwo.HwoError) as ei:
+        g.counts(0)
+    assert ei.value.code == hwo.HWO_EOVERFLOW
+    c = g.counts(0, allow_overflow=True)
+    assert c[0, 5] > 0
+    assert g.particles().shape[0] == 500
+    # the first step fits, so its counts are exact
+    g1, o1 = make(s)
+    g1.step(1)
+    o1.step(1)
+    check_integer_state(g1, o1, s)
+
+
+def test_empty_scene_and_zero_steps():
+    from paper_2511_02852_amd import hwo
+    s = scenes.Scene(name="empty", fft_n=32, fft_L=100.0, seed=1, spectrum=scenes.Spectrum(n_buckets=2))
+    g = hwo.Ocean(s)
+    g.step(0)
+    assert g.particles().shape[0] == 0
+    g.step(3)
+    o = oracle.Oracle(s)
+    o.step(3)
+    assert rel_rms(g.background(), o.background()) <= TOL
+
+
+def test_static_source_outside_patch_emits_dead_particles():
+    """A ring emitted outside its patch window dies at once (counted)."""
+    s = scenes.c1()
+    s.sources = [scenes.Source(x0=300.0, y0=300.0, vx=3.0, vy=0.0, radius=1.0, ring_n=32, patch=0)]
+    g, o = make(s)
+    g.step(10)
+    o.step(10)
+    check_integer_state(g, o, s)
+    assert o.counts(0)[:, 4].sum() > 0
