@@ -155,7 +155,8 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
 /* Per-stage timing (benchmark support).  enable != 0 brackets every kernel
  * launch with HIP events (graph replay is then disabled); hwo_stage_times
  * returns accumulated milliseconds and launch counts per stage:
- *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat */
+ *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat
+ *   7 splat_plan  8 splat_reduce  (n >= 9) */
 int hwo_set_timing(hwo_ocean *o, int32_t enable);
 int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
 /* Bytes of particle storage per record for the active form (16 or 32). */

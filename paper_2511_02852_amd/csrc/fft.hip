@@ -157,9 +157,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
       const int myn = (N - e) & (N - 1);
       float2 a = ha[e], b = hb[myn];
       float ky = dk * (float)signed_idx(e, N);
-      float w = sqrtf(g * sqrtf(fmaf(kx, kx, ky * ky)));
-      float s, c;
-      sincosf(w * tn, &s, &c);
+      // phase w t in revolutions, reduced to [-1/2, 1/2] for v_sin/v_cos
+      const float w = sqrtf(g * sqrtf(fmaf(kx, kx, ky * ky)));
+      float rev = w * tn * 0.159154943091895336f;
+      rev -= rintf(rev);
+      const float s = __builtin_amdgcn_sinf(rev), c = __builtin_amdgcn_cosf(rev);
       // a e^{-iwt} + conj(b) e^{+iwt}
       float re = fmaf(a.x + b.x, c, (a.y + b.y) * s);
       float im = fmaf(a.y - b.y, c, (b.x - a.x) * s);

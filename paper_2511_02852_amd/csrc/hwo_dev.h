@@ -143,6 +143,16 @@ struct Dev {
   float2 *FT;                  // [N/2+1][N]
   float *H;                    // [N][N]
   float *raw, *blend;          // heights, all patches
+  float dense_rc;              // buckets with radius >= dense_rc cells use the dense path
+  // splat work plan
+  const uint32_t *bcost;       // [nb] relative splat cost of one particle per bucket
+  uint32_t *tile_load;         // [ntiles] weighted particle count per output tile
+  int32_t *item_base;          // [ntiles + 1] first work item of each tile (plan)
+  int32_t *splat_ctl;          // [0] next item, [1] total items
+  float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
+  int32_t max_items;           // capacity of partials (items)
+  int32_t max_parts;           // parts per tile at most
+  uint32_t chunk_load;         // target load per work item
 };
 
 // ---------------------------------------------------------------- helpers
@@ -239,7 +249,9 @@ void launch_fft_b(const Dev &d, hipStream_t st);
 void launch_params(const Dev &d, hipStream_t st);
 void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st);
 void launch_scan(const Dev &d, int bin_lo, int bin_hi, bool first, bool last, hipStream_t st);
-void launch_splat_tiles(const Dev &d, int t0, int ntiles, hipStream_t st);
+void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipStream_t st);
+void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st);
+void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st);
 void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw,
                          int64_t out_off, hipStream_t st);
 void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, hipStream_t st);

@@ -162,11 +162,12 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
 // ---------------------------------------------------------------- update
 // Survival and bin key of a particle at age `age` (>= 0).  -1 if it dies.
 __device__ __forceinline__ int32_t survive_key(const Dev &d, const PatchDev &P, const StepPatch &W,
-                                               int bucket, int code, int32_t ox, int32_t oy, int32_t age) {
+                                               int bucket, int code, int32_t ox, int32_t oy, int32_t age,
+                                               int64_t &px, int64_t &py) {
   if (age > kAgeMax) return -1;
   const int2 v = d.V[bucket * kNCode + code];
-  const int64_t px = (int64_t)ox + (((int64_t)age * v.x) >> 12);
-  const int64_t py = (int64_t)oy + (((int64_t)age * v.y) >> 12);
+  px = (int64_t)ox + (((int64_t)age * v.x) >> 12);
+  py = (int64_t)oy + (((int64_t)age * v.y) >> 12);
   const int64_t m = d.margin[bucket];
   const int64_t lox = (int64_t)W.wx * P.dxu - m, hix = (int64_t)(W.wx + P.nx) * P.dxu + m;
   const int64_t loy = (int64_t)W.wy * P.dxu - m, hiy = (int64_t)(W.wy + P.ny) * P.dxu + m;
@@ -311,7 +312,8 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       const PatchDev &P = d.patches[pid];
       const StepPatch W = d.sp[pid];
       for (int r = 0; r < nout; ++r) {
-        key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age);
+        int64_t px, py;
+        key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age, px, py);
         if (!kScatter && key[r] < 0)
           atomicAdd(&d.ctr[((size_t)pid * d.nb + bkt) * CNT_NUM + CNT_DIED], 1ull);
       }

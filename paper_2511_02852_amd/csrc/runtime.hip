@@ -33,8 +33,8 @@ namespace {
 constexpr double kUnit = 1048576.0;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kTwo30 = 1073741824.0;
-constexpr int kStages = 7;
-enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT };
+constexpr int kStages = 9;
+enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE };
 
 int64_t pmod(int64_t a, int64_t m) {
   int64_t r = a % m;
@@ -83,6 +83,9 @@ struct hwo_ocean {
   float2 *h0T = nullptr, *tw = nullptr;
   uint32_t *cdf = nullptr, *cdfQ = nullptr;
   int update_grid = 1024;
+  int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
+  int items_target = 512;          // splat work items per frame the plan aims for (beyond one per tile)
+  float dense_rc = 12.f;           // radius (cells) from which the dense splat path is used
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // timing
@@ -551,6 +554,28 @@ static int finalize(hwo_ocean *o) {
   d.H = (float *)o->alloc(sizeof(float) * (size_t)N * N);
   d.raw = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
+  // splat work plan
+  d.dense_rc = o->dense_rc;
+  {
+    double dxmin = 1e30;
+    for (auto &hp : o->patches) dxmin = std::min(dxmin, hp.dx);
+    std::vector<uint32_t> bc(nb);
+    for (int i = 0; i < nb; ++i) {
+      const double rc = o->r[i] / dxmin;
+      bc[i] = (uint32_t)std::min(1.0 + floor((2.0 * rc + 1.0) * (2.0 * rc + 1.0) / 32.0), 65535.0);
+    }
+    d.bcost = upload(o, bc, &rc);
+    if (rc) return rc;
+  }
+  d.max_items = d.ntiles + 4096;
+  d.max_parts = 64;
+  d.chunk_load = 256;
+  d.tile_load = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
+  d.item_base = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.ntiles + 1));
+  d.splat_ctl = (int32_t *)o->alloc(sizeof(int32_t) * 2);
+  d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
+  if (!d.tile_load || !d.item_base || !d.splat_ctl || !d.partials)
+    return o->fail(HWO_ENOMEM, "device allocation failed");
   if (!d.glob || !d.sp || !d.inj_off || !d.em_off || !d.src_pos || !d.ctr || !d.hist || !d.off || !d.cur ||
       !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
     return o->fail(HWO_ENOMEM, "device allocation failed");
@@ -562,11 +587,15 @@ static int finalize(hwo_ocean *o) {
   HWO_CHECK(hipMemsetAsync(d.raw, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.blend, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.H, 0, sizeof(float) * (size_t)N * N, o->st));
+  HWO_CHECK(hipMemsetAsync(d.tile_load, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.item_base, 0, sizeof(int32_t) * ((size_t)d.ntiles + 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.splat_ctl, 0, sizeof(int32_t) * 2, o->st));
   HWO_CHECK(hipStreamSynchronize(o->st));
   int dev_id = 0, cus = 256;
   (void)hipGetDevice(&dev_id);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
   o->update_grid = std::max(64, 4 * cus);
+  o->target_blocks = std::max(64, 4 * cus);
   o->finalized = true;
   return HWO_OK;
 }
@@ -588,9 +617,10 @@ static void timed(hwo_ocean *o, int stage, void (*fn)(hwo_ocean *, void *), void
 }
 
 struct PatchArg {
-  int p0, p1;
-  int b0, b1;
+  int p0, p1;     // patch range
+  int b0, b1;     // bin range
   bool first, last;
+  int t0, t1;     // output tile range
 };
 
 static void run_step(hwo_ocean *o) {
@@ -602,10 +632,10 @@ static void run_step(hwo_ocean *o) {
   if (d.np == 0) return;
   std::vector<PatchArg> groups;
   if (o->cfg.batched) {
-    groups.push_back({0, d.np, 0, d.nbins, true, true});
+    groups.push_back({0, d.np, 0, d.nbins, true, true, 0, 0});
   } else {
     for (int p = 0; p < d.np; ++p)
-      groups.push_back({p, p + 1, o->pdev[p].bin_lo, o->pdev[p].bin_hi, p == 0, p == d.np - 1});
+      groups.push_back({p, p + 1, o->pdev[p].bin_lo, o->pdev[p].bin_hi, p == 0, p == d.np - 1, 0, 0});
   }
   for (auto &gp : groups) {
     timed(o, ST_COUNT, [](hwo_ocean *oo, void *a) {
@@ -622,12 +652,23 @@ static void run_step(hwo_ocean *o) {
     }, &gp);
   }
   for (auto &gp : groups) {
+    const PatchDev &P0 = o->pdev[gp.p0];
+    const PatchDev &P1 = o->pdev[gp.p1 - 1];
+    gp.t0 = P0.tile0;
+    gp.t1 = P1.tile0 + P1.ntx * P1.nty;
+    timed(o, ST_PLAN, [](hwo_ocean *oo, void *a) {
+      auto *g = (PatchArg *)a;
+      launch_splat_plan(oo->dev, g->t0, g->t1 - g->t0, oo->items_target, oo->st);
+    }, &gp);
     timed(o, ST_SPLAT, [](hwo_ocean *oo, void *a) {
       auto *g = (PatchArg *)a;
-      const PatchDev &P0 = oo->pdev[g->p0];
-      const PatchDev &P1 = oo->pdev[g->p1 - 1];
-      const int t0 = P0.tile0, t1 = P1.tile0 + P1.ntx * P1.nty;
-      launch_splat_tiles(oo->dev, t0, t1 - t0, oo->st);
+      const int nt = g->t1 - g->t0;
+      const int grid = std::max(1, std::min(2 * oo->target_blocks, nt * oo->dev.max_parts));
+      launch_splat_tiles(oo->dev, g->t0, nt, grid, oo->st);
+    }, &gp);
+    timed(o, ST_REDUCE, [](hwo_ocean *oo, void *a) {
+      auto *g = (PatchArg *)a;
+      launch_splat_reduce(oo->dev, g->t0, g->t1 - g->t0, oo->st);
     }, &gp);
   }
   (void)st;

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libhwo.so")
 
 HWO_OK, HWO_EINVAL, HWO_ESTATE, HWO_ENOMEM, HWO_EDEVICE, HWO_ERANGE, HWO_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
-STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat"]
+STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "splat_plan", "splat_reduce"]
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
@@ -66,6 +66,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise HwoError(HWO_EDEVICE, f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    # PyTorch ships its own HIP runtime under the same soname; load it first so
+    # the library binds to that runtime and shares torch's streams and memory.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, P = C.c_void_p, C.c_int32, C.c_int64, C.POINTER
     sig = {
