@@ -148,6 +148,8 @@ struct Dev {
   const uint32_t *bcost;       // [nb] relative splat cost of one particle per bucket
   uint32_t *tile_load;         // [ntiles] weighted particle count per output tile
   int32_t *item_base;          // [ntiles + 1] first work item of each tile (plan)
+  uint32_t *item_tile;         // [max_items] tile << 12 | part << 6 | (parts - 1) (plan)
+  const int32_t *tile_patch;   // [ntiles] patch of each output tile
   int32_t *splat_ctl;          // [0] next item, [1] total items
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
   int32_t max_items;           // capacity of partials (items)

@@ -84,7 +84,7 @@ struct hwo_ocean {
   uint32_t *cdf = nullptr, *cdfQ = nullptr;
   int update_grid = 1024;
   int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
-  int items_target = 512;          // splat work items per frame the plan aims for (beyond one per tile)
+  int items_target = 2048;          // splat work items per frame the plan aims for (beyond one per tile)
   float dense_rc = 12.f;           // radius (cells) from which the dense splat path is used
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -382,6 +382,9 @@ static int build_scene_tables(hwo_ocean *o) {
       P.nby[i] = (int32_t)(floor_div((int64_t)hp.ny * P.dxu + 2 * m, binu) + 1);
       P.binbase[i] = (int32_t)bins;
       bins += (int64_t)P.nbx[i] * P.nby[i];
+      // a 64-cell splat tile must reach its crests through at most 32 bin rows
+      if ((63 * (int64_t)P.dxu + 2 * m) / binu + 2 > 32)
+        return o->fail(HWO_EINVAL, "bin edge too small for the bucket radius (a tile would need > 32 bin rows)");
       if (bins > ((int64_t)1 << 28)) return o->fail(HWO_EINVAL, "too many bins");
     }
     P.bin_hi = (int32_t)bins;
@@ -389,6 +392,7 @@ static int build_scene_tables(hwo_ocean *o) {
     P.nty = (hp.ny + kTile - 1) / kTile;
     P.tile0 = (int32_t)tiles;
     tiles += (int64_t)P.ntx * P.nty;
+    if (tiles > ((int64_t)1 << 19)) return o->fail(HWO_EINVAL, "too many output tiles");
     P.cell0 = cells;
     cells += (int64_t)hp.nx * hp.ny;
   }
@@ -573,6 +577,15 @@ static int finalize(hwo_ocean *o) {
   d.tile_load = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
   d.item_base = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.ntiles + 1));
   d.splat_ctl = (int32_t *)o->alloc(sizeof(int32_t) * 2);
+  d.item_tile = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)d.max_items);
+  {
+    std::vector<int32_t> tp((size_t)std::max(d.ntiles, 1), 0);
+    for (int p = 0; p < np; ++p)
+      for (int t = 0; t < o->pdev[p].ntx * o->pdev[p].nty; ++t) tp[(size_t)o->pdev[p].tile0 + t] = p;
+    d.tile_patch = upload(o, tp, &rc);
+    if (rc) return rc;
+  }
+  if (!d.item_tile) return o->fail(HWO_ENOMEM, "device allocation failed");
   d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
   if (!d.tile_load || !d.item_base || !d.splat_ctl || !d.partials)
     return o->fail(HWO_ENOMEM, "device allocation failed");

@@ -36,7 +36,7 @@ namespace hwo {
 
 namespace {
 
-constexpr int kBatch = 32;   // dense-path items (crests + troughs) per batch
+constexpr int kBatch = 16;   // dense-path items (crests + troughs) per batch
 constexpr int kPad = kTile + 1;
 
 __device__ __forceinline__ void wave_fence() {
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) 
   const int lane = threadIdx.x & 63;
   if (t >= nt) return;
   const int tile = t0 + t;
-  const int p = patch_of_tile(d, tile);
+  const int p = d.tile_patch[tile];
   const PatchDev &P = d.patches[p];
   const int lt = tile - P.tile0;
   const int tx = lt % P.ntx, ty = lt / P.ntx;
@@ -214,8 +214,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
   int32_t acc = pre + inc - cnt;
   for (int t = beg; t < end; ++t) {
     const uint32_t l = d.tile_load[t0 + t];
+    const int parts = min(d.max_parts, 1 + (int32_t)(l / chunk));
     d.item_base[t0 + t] = acc;
-    acc += min(d.max_parts, 1 + (int32_t)(l / chunk));
+    for (int j = 0; j < parts; ++j)
+      d.item_tile[acc + j] = ((uint32_t)(t0 + t) << 12) | ((uint32_t)j << 6) | (uint32_t)(parts - 1);
+    acc += parts;
   }
   if (tid == kPlanThreads - 1) {
     d.item_base[t0 + nt] = acc;
@@ -224,6 +227,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
 }
 
 // ---------------------------------------------------------------- splat
+constexpr int kChunk = kThreads;   // particles decoded into LDS per step
+constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
+
 template <class Rec>
 __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
                                                     int ndirect, float *__restrict__ raw_out,
@@ -232,9 +238,17 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
   __shared__ float scratch[kThreads / 64][64];
   __shared__ float4 wx4[kBatch][kTile / 4];
   __shared__ float4 wy4[kBatch][kTile / 4];
-  __shared__ float it_cx[kBatch], it_cy[kBatch], it_a[kBatch];
-  __shared__ int it_j0[kBatch], it_j1[kBatch];
-  __shared__ int s_tile, s_part, s_nparts;
+  // decoded chunk: crest centre (tile cells), amplitude, direction
+  __shared__ float dc_x[kChunk], dc_y[kChunk], dc_a[kChunk], dc_ux[kChunk], dc_uy[kChunk];
+  __shared__ uint16_t it_idx[2 * kChunk];    // dense items: particle | 0x8000 for the trough
+  // per bucket: bin rows reaching the tile (start, exclusive prefix of lengths)
+  __shared__ int s_rlo[kMaxBuckets][kMaxRows];
+  __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
+  __shared__ int s_nrows[kMaxBuckets];
+  __shared__ int s_bstart[kMaxBuckets];      // first index of this part in the bucket's list
+  __shared__ int s_boff[kMaxBuckets + 1];    // offsets of the buckets in the item's list
+  __shared__ int s_wcnt[kThreads / 64];
+  __shared__ int s_tile, s_part, s_nparts, s_patch;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -243,89 +257,148 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
   const int64_t n = d.glob->n;
   const Rec *__restrict__ S = direct ? direct : (const Rec *)((n & 1) ? d.S1 : d.S0);
   const int total = direct ? nt : d.splat_ctl[1];
+  const int nb = d.nb;
   // dense-path ownership: 4x4 cells per thread, wave w owns rows 16w..16w+15
   const int dc0 = 4 * (lane & 15);
   const int dr0 = 16 * wave + 4 * (lane >> 4);
 
   for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
     if (tid == 0) {
+      int tile, part, np_;
       if (direct) {
-        s_tile = t0 + item;
-        s_part = 0;
-        s_nparts = 1;
+        tile = t0 + item;
+        part = 0;
+        np_ = 1;
       } else {
-        int lo = 0, hi = nt - 1;   // last tile with item_base <= item
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (d.item_base[t0 + mid] <= item) lo = mid; else hi = mid - 1;
-        }
-        s_tile = t0 + lo;
-        s_part = item - d.item_base[t0 + lo];
-        s_nparts = d.item_base[t0 + lo + 1] - d.item_base[t0 + lo];
+        const uint32_t e = d.item_tile[item];
+        tile = (int)(e >> 12);
+        part = (int)((e >> 6) & 63);
+        np_ = (int)(e & 63) + 1;
       }
+      s_tile = tile;
+      s_part = part;
+      s_nparts = np_;
+      s_patch = d.tile_patch[tile];
     }
     for (int c = tid; c < kTile * kPad; c += kThreads) (&acc[0][0])[c] = 0.f;
     __syncthreads();
     const int tile = s_tile, part = s_part, nparts = s_nparts;
     TileGeom T;
-    tile_geom(d, tile, patch_of_tile(d, tile), T);
+    tile_geom(d, tile, s_patch, T);
     const PatchDev &P = d.patches[T.p];
     const int32_t dxu = P.dxu;
+    const int64_t ax0 = (int64_t)T.i0 * dxu + dxu / 2;
+    const int64_t ay0 = (int64_t)T.j0 * dxu + dxu / 2;
+
+    // ---- row tables of every bucket, loaded in one pass
+    for (int q = tid; q < nb * kMaxRows; q += kThreads) {
+      const int b = q / kMaxRows, r = q % kMaxRows;
+      int nrows, lo = 0, len = 0;
+      if (direct) {
+        nrows = 1;
+        if (r == 0) len = ndirect;
+      } else {
+        const int32_t m = d.margin[b];
+        const int32_t binu = P.binu[b];
+        const int bx_lo = (int)(ax0 / binu);
+        const int bx_hi = min(P.nbx[b] - 1, (int)((ax0 + (int64_t)(T.tw - 1) * dxu + 2 * (int64_t)m) / binu));
+        const int by_lo = (int)(ay0 / binu);
+        const int by_hi = min(P.nby[b] - 1, (int)((ay0 + (int64_t)(T.th - 1) * dxu + 2 * (int64_t)m) / binu));
+        nrows = (bx_lo <= bx_hi && by_lo <= by_hi) ? min(by_hi - by_lo + 1, kMaxRows) : 0;
+        if (r < nrows) {
+          const int rb = P.binbase[b] + (by_lo + r) * P.nbx[b];
+          lo = min(d.off[rb + bx_lo], d.cap);
+          len = max(0, min(d.off[rb + bx_hi + 1], d.cap) - lo);
+        }
+      }
+      if (r < nrows) {
+        s_rlo[b][r] = lo;
+        s_pre[b][r] = len;
+      }
+      if (r == 0) s_nrows[b] = nrows;
+    }
+    __syncthreads();
+    // exclusive prefix of the row lengths, one bucket per wave
+    for (int b = wave; b < nb; b += nwaves) {
+      const int nrows = s_nrows[b];
+      const int len = lane < nrows ? s_pre[b][lane] : 0;
+      int inc = len;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+      }
+      if (lane < nrows) s_pre[b][lane] = inc - len;
+      if (lane == 63) s_pre[b][nrows] = inc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int accum = 0;
+      for (int b = 0; b < nb; ++b) {
+        const int M = s_pre[b][s_nrows[b]];
+        const int p0 = (int)((int64_t)M * part / nparts), p1 = (int)((int64_t)M * (part + 1) / nparts);
+        s_bstart[b] = p0;
+        s_boff[b] = accum;
+        accum += p1 - p0;
+      }
+      s_boff[nb] = accum;
+    }
+    __syncthreads();
+    const int Mi = s_boff[nb];
     float racc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) racc[i][j] = 0.f;
 
-    for (int b = 0; b < d.nb; ++b) {
-      const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
-      const float inv_rc = 1.f / rc;
-      const bool dense = rc >= d.dense_rc;
-      T.Ab = P.A[b];
-      // bin rows / columns whose crests can reach the tile
-      int nrange, by_lo = 0, bx_lo = 0, bx_hi = 0, row0 = 0;
-      if (direct) {
-        nrange = 1;
-      } else {
-        const int32_t m = d.margin[b];
-        const int32_t binu = P.binu[b];
-        const int64_t ax0 = (int64_t)T.i0 * dxu + dxu / 2;
-        const int64_t ay0 = (int64_t)T.j0 * dxu + dxu / 2;
-        bx_lo = (int)(ax0 / binu);
-        bx_hi = min(P.nbx[b] - 1, (int)((ax0 + (int64_t)(T.tw - 1) * dxu + 2 * (int64_t)m) / binu));
-        by_lo = (int)(ay0 / binu);
-        const int by_hi = min(P.nby[b] - 1, (int)((ay0 + (int64_t)(T.th - 1) * dxu + 2 * (int64_t)m) / binu));
-        nrange = (bx_lo <= bx_hi && by_lo <= by_hi) ? by_hi - by_lo + 1 : 0;
-        row0 = P.binbase[b];
-      }
-      int need = (int)floorf(2.f * rc) + 1;
-      int lg = 0;
-      while ((1 << lg) < need && lg < 6) ++lg;
-      const int G = 1 << lg, ppw = 64 >> lg;
-      const int grp = lane >> lg, gl = lane & (G - 1);
-
-      for (int rr = 0; rr < nrange; ++rr) {
-        int lo, hi;
-        if (direct) {
-          lo = 0;
-          hi = ndirect;
-        } else {
-          const int rb = row0 + (by_lo + rr) * P.nbx[b];
-          lo = min(d.off[rb + bx_lo], d.cap);
-          hi = min(d.off[rb + bx_hi + 1], d.cap);
+    for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
+      const int m = min(kChunk, Mi - c);
+      // ---- decode: item-list index -> bucket -> bin row -> particle (one per thread)
+      if (tid < m) {
+        const int g = c + tid;
+        int b = 0;
+        while (b + 1 < nb && s_boff[b + 1] <= g) ++b;
+        const int v = s_bstart[b] + (g - s_boff[b]);
+        int lo = 0, hi = s_nrows[b] - 1;   // last row with prefix <= v
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
         }
-        if (hi <= lo) continue;
-        if (!dense) {
+        const int k = s_rlo[b][lo] + (v - s_pre[b][lo]);
+        float cx = 0.f, cy = 0.f, A = 0.f;
+        float2 u = make_float2(0.f, 0.f);
+        TileGeom Tb = T;
+        Tb.Ab = P.A[b];
+        const bool valid = load_item<Rec>(d, S, k, n, b, Tb, cx, cy, A, u);
+        dc_x[tid] = cx;
+        dc_y[tid] = cy;
+        dc_a[tid] = valid ? A : 0.f;
+        dc_ux[tid] = u.x;
+        dc_uy[tid] = u.y;
+      }
+      __syncthreads();
+      // ---- the chunk holds runs of consecutive buckets
+      for (int b = 0; b < nb; ++b) {
+        const int seg_lo = max(c, s_boff[b]) - c, seg_hi = min(c + m, s_boff[b + 1]) - c;
+        if (seg_hi <= seg_lo) continue;   // block-uniform
+        const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
+        const float inv_rc = 1.f / rc;
+        if (rc < d.dense_rc) {
           // ---- group scatter: one crest/trough per group of G lanes
-          for (int k0 = lo + (part * nwaves + wave) * ppw; k0 < hi; k0 += nparts * nwaves * ppw) {
-            const int k = k0 + grp;
-            float cx = 0.f, cy = 0.f, A = 0.f;
-            float2 u = make_float2(0.f, 0.f);
-            const bool valid = (k < hi) && load_item<Rec>(d, S, k, n, b, T, cx, cy, A, u);
+          int need = (int)floorf(2.f * rc) + 1;
+          int lg = 0;
+          while ((1 << lg) < need && lg < 6) ++lg;
+          const int G = 1 << lg, ppw = 64 >> lg;
+          const int grp = lane >> lg, gl = lane & (G - 1);
+          for (int i0 = seg_lo + wave * ppw; i0 < seg_hi; i0 += nwaves * ppw) {
+            const int i = i0 + grp;
+            const bool valid = i < seg_hi && dc_a[i] != 0.f;
+            const float cx = valid ? dc_x[i] : 0.f, cy = valid ? dc_y[i] : 0.f;
+            const float A = valid ? dc_a[i] : 0.f;
+            const float ux = valid ? dc_ux[i] : 0.f, uy = valid ? dc_uy[i] : 0.f;
 #pragma unroll
             for (int pass = 0; pass < 2; ++pass) {
-              const float ccx = pass ? cx - rc * u.x : cx;
-              const float ccy = pass ? cy - rc * u.y : cy;
+              const float ccx = pass ? cx - rc * ux : cx;
+              const float ccy = pass ? cy - rc * uy : cy;
               const float amp = pass ? -A : A;
               int nr = 0, nc = 0, ilo = 0, jlo = 0;
               if (valid) {
@@ -358,43 +431,52 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
             }
           }
         } else {
-          // ---- dense rank-K update over batches of kBatch/2 particles
-          for (int c0 = lo + part * (kBatch / 2); c0 < hi; c0 += nparts * (kBatch / 2)) {
-            if (tid < kBatch / 2) {
-              const int k = c0 + tid;
-              float cx = 0.f, cy = 0.f, A = 0.f;
-              float2 u = make_float2(0.f, 0.f);
-              const bool valid = (k < hi) && load_item<Rec>(d, S, k, n, b, T, cx, cy, A, u);
-              const float tx = cx - rc * u.x, ty = cy - rc * u.y;
-              it_cx[2 * tid] = cx;
-              it_cy[2 * tid] = cy;
-              it_a[2 * tid] = valid ? A : 0.f;
-              it_cx[2 * tid + 1] = tx;
-              it_cy[2 * tid + 1] = ty;
-              it_a[2 * tid + 1] = valid ? -A : 0.f;
-              it_j0[2 * tid] = valid ? max(0, (int)ceilf(cy - rc)) : kTile;
-              it_j1[2 * tid] = valid ? min(T.th - 1, (int)floorf(cy + rc)) : -1;
-              it_j0[2 * tid + 1] = valid ? max(0, (int)ceilf(ty - rc)) : kTile;
-              it_j1[2 * tid + 1] = valid ? min(T.th - 1, (int)floorf(ty + rc)) : -1;
-            }
-            __syncthreads();
-            // weight vectors: kBatch items x (64 x-weights, 64 y-weights)
-            for (int v = tid; v < kBatch * 2 * kTile; v += kThreads) {
-              const int it = v / (2 * kTile), which = (v / kTile) & 1, pos = v % kTile;
+          // ---- dense rank-K update: keep only crests/troughs that overlap the tile
+          int nmine = 0;
+          bool oc = false, ot = false;
+          if (tid >= seg_lo && tid < seg_hi && dc_a[tid] != 0.f) {
+            const float cx = dc_x[tid], cy = dc_y[tid];
+            const float tx = cx - rc * dc_ux[tid], ty = cy - rc * dc_uy[tid];
+            oc = cx + rc >= 0.f && cx - rc <= (float)(T.tw - 1) && cy + rc >= 0.f && cy - rc <= (float)(T.th - 1);
+            ot = tx + rc >= 0.f && tx - rc <= (float)(T.tw - 1) && ty + rc >= 0.f && ty - rc <= (float)(T.th - 1);
+            nmine = (oc ? 1 : 0) + (ot ? 1 : 0);
+          }
+          int inc = nmine;
+          for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+          }
+          if (lane == 63) s_wcnt[wave] = inc;
+          __syncthreads();
+          int base = 0, nitems = 0;
+          for (int w = 0; w < nwaves; ++w) {
+            if (w < wave) base += s_wcnt[w];
+            nitems += s_wcnt[w];
+          }
+          int pos = base + inc - nmine;
+          if (oc) it_idx[pos++] = (uint16_t)tid;
+          if (ot) it_idx[pos] = (uint16_t)(tid | 0x8000);
+          __syncthreads();
+          for (int ib = 0; ib < nitems; ib += kBatch) {   // block-uniform
+            const int nbatch = min(kBatch, nitems - ib);
+            for (int vv = tid; vv < nbatch * 2 * kTile; vv += kThreads) {
+              const int it = vv / (2 * kTile), which = (vv / kTile) & 1, q = vv % kTile;
+              const int e = it_idx[ib + it], pi = e & 0x7FFF;
+              const bool tr = (e & 0x8000) != 0;
               if (which == 0) {
-                reinterpret_cast<float *>(&wx4[it][0])[pos] =
-                    (pos < T.tw) ? it_a[it] * wcos(((float)pos - it_cx[it]) * inv_rc) : 0.f;
+                const float ccx = tr ? dc_x[pi] - rc * dc_ux[pi] : dc_x[pi];
+                const float amp = tr ? -dc_a[pi] : dc_a[pi];
+                reinterpret_cast<float *>(&wx4[it][0])[q] = (q < T.tw) ? amp * wcos(((float)q - ccx) * inv_rc) : 0.f;
               } else {
-                reinterpret_cast<float *>(&wy4[it][0])[pos] =
-                    (pos < T.th) ? wcos(((float)pos - it_cy[it]) * inv_rc) : 0.f;
+                const float ccy = tr ? dc_y[pi] - rc * dc_uy[pi] : dc_y[pi];
+                reinterpret_cast<float *>(&wy4[it][0])[q] = (q < T.th) ? wcos(((float)q - ccy) * inv_rc) : 0.f;
               }
             }
             __syncthreads();
-            const int band0 = 16 * wave, band1 = band0 + 15;
-            for (int it = 0; it < kBatch; ++it) {
-              if (it_j1[it] < band0 || it_j0[it] > band1) continue;   // wave-uniform
-              const float4 xv = wx4[it][dc0 >> 2];
+            for (int it = 0; it < nbatch; ++it) {
               const float4 yv = wy4[it][dr0 >> 2];
+              if (yv.x == 0.f && yv.y == 0.f && yv.z == 0.f && yv.w == 0.f) continue;
+              const float4 xv = wx4[it][dc0 >> 2];
               const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
               const float ys[4] = {yv.x, yv.y, yv.z, yv.w};
 #pragma unroll
@@ -406,8 +488,8 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
           }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -440,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_reduce(Dev d, int t0, int nt
   const int base = d.item_base[tile], np_ = d.item_base[tile + 1] - base;
   if (np_ <= 1) return;
   TileGeom T;
-  tile_geom(d, tile, patch_of_tile(d, tile), T);
+  tile_geom(d, tile, d.tile_patch[tile], T);
   const PatchDev &P = d.patches[T.p];
   const StepPatch &W = d.sp[T.p];
   const int j = 4 * q + ((int)threadIdx.x >> 6), i = threadIdx.x & 63;

@@ -127,7 +127,7 @@ def default_bins(n_buckets: int, lambda_min: float, lambda_max: float, dx: float
         lam = lambda_min * (lambda_max / lambda_min) ** ((i + 0.5) / n_buckets)
         cells = lam / dx  # roughly two radii
         b = 8
-        while b < cells and b < 128:
+        while b < cells and b < 32:
             b *= 2
         out.append(b)
     return out
