@@ -75,6 +75,7 @@ struct PatchDev {
   double ax, ay, dx;
   int32_t nx, ny, dxu, follow;
   float band, ratio;           // blend band (m); dx / background cell
+  float inv_band;
   int32_t bin_lo, bin_hi;      // bins of this patch in the global histogram
   int32_t tile0, ntx, nty;     // splat output tiles
   int32_t src_lo, src_hi;      // range in the patch-sorted source list
@@ -143,17 +144,15 @@ struct Dev {
   float2 *FT;                  // [N/2+1][N]
   float *H;                    // [N][N]
   float *raw, *blend;          // heights, all patches
-  float dense_rc;              // buckets with radius >= dense_rc cells use the dense path
   // splat work plan
-  const uint32_t *bcost;       // [nb] relative splat cost of one particle per bucket
   uint32_t *tile_load;         // [ntiles] weighted particle count per output tile
   int32_t *item_base;          // [ntiles + 1] first work item of each tile (plan)
-  uint32_t *item_tile;         // [max_items] tile << 12 | part << 6 | (parts - 1) (plan)
+  int32_t *item_tile;          // [max_items] tile of each work item (plan)
   const int32_t *tile_patch;   // [ntiles] patch of each output tile
+  const short4 *tile_rect;     // [ntiles][nb] bins reaching the tile: bx_lo, bx_hi, by_lo, nrows
   int32_t *splat_ctl;          // [0] next item, [1] total items
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
   int32_t max_items;           // capacity of partials (items)
-  int32_t max_parts;           // parts per tile at most
   uint32_t chunk_load;         // target load per work item
 };
 

@@ -85,7 +85,6 @@ struct hwo_ocean {
   int update_grid = 1024;
   int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
   int items_target = 2048;          // splat work items per frame the plan aims for (beyond one per tile)
-  float dense_rc = 12.f;           // radius (cells) from which the dense splat path is used
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // timing
@@ -362,6 +361,7 @@ static int build_scene_tables(hwo_ocean *o) {
     const double rmax = o->r[nb - 1];
     const double lmin = (double)(hp.nx < hp.ny ? hp.nx : hp.ny) * hp.dx / 4.0;
     P.band = (float)((hp.blend_band > 0.0) ? hp.blend_band : (rmax < lmin ? rmax : lmin));
+    P.inv_band = 1.0f / P.band;
     P.ratio = (float)(hp.dx / dxf);
     const double Lx = (double)hp.nx * hp.dx, Ly = (double)hp.ny * hp.dx;
     P.bin_lo = (int32_t)bins;
@@ -559,30 +559,41 @@ static int finalize(hwo_ocean *o) {
   d.raw = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   // splat work plan
-  d.dense_rc = o->dense_rc;
-  {
-    double dxmin = 1e30;
-    for (auto &hp : o->patches) dxmin = std::min(dxmin, hp.dx);
-    std::vector<uint32_t> bc(nb);
-    for (int i = 0; i < nb; ++i) {
-      const double rc = o->r[i] / dxmin;
-      bc[i] = (uint32_t)std::min(1.0 + floor((2.0 * rc + 1.0) * (2.0 * rc + 1.0) / 32.0), 65535.0);
-    }
-    d.bcost = upload(o, bc, &rc);
-    if (rc) return rc;
-  }
   d.max_items = d.ntiles + 4096;
-  d.max_parts = 64;
   d.chunk_load = 256;
   d.tile_load = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
   d.item_base = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.ntiles + 1));
   d.splat_ctl = (int32_t *)o->alloc(sizeof(int32_t) * 2);
-  d.item_tile = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)d.max_items);
+  d.item_tile = (int32_t *)o->alloc(sizeof(int32_t) * (size_t)d.max_items);
   {
     std::vector<int32_t> tp((size_t)std::max(d.ntiles, 1), 0);
     for (int p = 0; p < np; ++p)
       for (int t = 0; t < o->pdev[p].ntx * o->pdev[p].nty; ++t) tp[(size_t)o->pdev[p].tile0 + t] = p;
     d.tile_patch = upload(o, tp, &rc);
+    if (rc) return rc;
+    // Bin rectangle each (tile, bucket) reads: crests within 2 r of the
+    // tile's cell centres, in bins anchored at the window origin minus 2 r.
+    // Static, because bins move with the window.
+    std::vector<short4> rect((size_t)std::max(d.ntiles, 1) * nb);
+    for (int p = 0; p < np; ++p) {
+      const PatchDev &P = o->pdev[p];
+      for (int t = 0; t < P.ntx * P.nty; ++t) {
+        const int i0 = (t % P.ntx) * kTile, j0 = (t / P.ntx) * kTile;
+        const int tw = std::min(kTile, P.nx - i0), th = std::min(kTile, P.ny - j0);
+        for (int b = 0; b < nb; ++b) {
+          const int64_t m = o->margin[b], binu = P.binu[b];
+          const int64_t ax0 = (int64_t)i0 * P.dxu + P.dxu / 2, ay0 = (int64_t)j0 * P.dxu + P.dxu / 2;
+          const int bx_lo = (int)(ax0 / binu);
+          const int bx_hi = (int)std::min<int64_t>(P.nbx[b] - 1, (ax0 + (int64_t)(tw - 1) * P.dxu + 2 * m) / binu);
+          const int by_lo = (int)(ay0 / binu);
+          const int by_hi = (int)std::min<int64_t>(P.nby[b] - 1, (ay0 + (int64_t)(th - 1) * P.dxu + 2 * m) / binu);
+          const int nrows = (bx_lo <= bx_hi && by_lo <= by_hi) ? by_hi - by_lo + 1 : 0;
+          if (nrows > 32 || bx_hi > 32767) return o->fail(HWO_EINVAL, "bin rectangle too large");
+          rect[((size_t)P.tile0 + t) * nb + b] = make_short4((short)bx_lo, (short)bx_hi, (short)by_lo, (short)nrows);
+        }
+      }
+    }
+    d.tile_rect = upload(o, rect, &rc);
     if (rc) return rc;
   }
   if (!d.item_tile) return o->fail(HWO_ENOMEM, "device allocation failed");
@@ -676,7 +687,7 @@ static void run_step(hwo_ocean *o) {
     timed(o, ST_SPLAT, [](hwo_ocean *oo, void *a) {
       auto *g = (PatchArg *)a;
       const int nt = g->t1 - g->t0;
-      const int grid = std::max(1, std::min(2 * oo->target_blocks, nt * oo->dev.max_parts));
+      const int grid = std::max(1, std::min(4 * oo->target_blocks, oo->dev.max_items));
       launch_splat_tiles(oo->dev, g->t0, nt, grid, oo->st);
     }, &gp);
     timed(o, ST_REDUCE, [](hwo_ocean *oo, void *a) {

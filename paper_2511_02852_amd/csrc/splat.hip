@@ -11,22 +11,24 @@
 // (Sec 3.1 local replacement, smooth distance weights of Sec 4.2).
 //
 // Work decomposition.  The output of every patch is cut into 64x64 tiles.
-// The particle scatter adds a weighted crest count per tile (cost weight per
-// bucket ~ footprint area); k_splat_plan turns these loads into a number of
-// parts per tile (about equal load per part, within a total item budget) and
-// a prefix of work items.  k_splat is a persistent grid over the items: an
-// item is one part of one tile, i.e. one of `nparts` interleaved shares of
-// the particles that can reach that tile.  For each bucket it walks the
-// particle bins whose crests lie within 2 r_b of the tile, which are
-// contiguous runs of the bin-sorted particle buffer:
-//   * small and medium radii: a group of G lanes (G ~ footprint width, a
-//     power of two) takes one crest or trough; its lanes write the row
-//     weights to a per-wave scratch, then own columns and add
-//     A w(d_x) w(d_y) into the LDS tile with LDS float atomics;
-//   * large radii (r >= dense_rc cells): the tile is a rank-K update,
-//     H += W_y^T (A W_x), over batches of 32 crests/troughs whose weight
-//     vectors are staged in LDS; each thread keeps a 4x4 block of the tile in
-//     registers (16 FMA per item, two 16-byte LDS reads).
+// k_splat_load estimates each tile's cost from the particles its items will
+// visit (bin offsets of this step, weighted by path); k_splat_plan turns the
+// loads into a number of parts per tile (about equal cost per part, within a
+// total item budget) and a prefix of work items.  k_splat is a grid over the
+// items: an item is one part of one tile, i.e. one of `nparts` equal shares
+// of each bucket's list of particles that can reach the tile.  That list is
+// the bins whose crests lie within 2 r_b of the tile, contiguous runs of the
+// bin-sorted particle buffer.  The item decodes 256 particles at a time into
+// LDS (crest and trough centres in tile cells, signed amplitudes) and then
+// runs each bucket's run of points through one of two paths:
+//   * footprints of at most 7 cells per axis: one point per lane, weights in
+//     registers, A w(d_x) w(d_y) added to the LDS tile with LDS float atomics;
+//   * larger footprints: the separable kernel makes the tile a sum of outer
+//     products, H += W_y^T (A W_x).  Each wavefront owns a 32x32 quadrant and
+//     feeds the points that reach it, two at a time, to a 32x32x2 FP32
+//     matrix-core product; every lane computes the one row weight and the
+//     one column weight it supplies.  The quadrant accumulators are added to
+//     the LDS tile at the end of the item.
 // A tile with one part is blended and written straight from LDS.  Parts of a
 // split tile store their partial tile; k_splat_reduce (the next launch, so
 // every store is visible on every XCD) sums them and runs the blend.
@@ -36,14 +38,7 @@ namespace hwo {
 
 namespace {
 
-constexpr int kBatch = 16;   // dense-path items (crests + troughs) per batch
 constexpr int kPad = kTile + 1;
-
-__device__ __forceinline__ void wave_fence() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Raised cosine w(t r) for t = d / r: cos^2(pi t / 2) on |t| < 1, else 0.
 // v_cos_f32 takes its argument in revolutions: cos(pi t / 2) = cos(2 pi t / 4).
@@ -114,7 +109,7 @@ __device__ __forceinline__ void blend_store(const Dev &d, const PatchDev &P, con
   const float dx = (float)P.dx;
   const float dd = fminf(fminf((float)ci + 0.5f, (float)P.nx - (float)ci - 0.5f),
                          fminf((float)cj + 0.5f, (float)P.ny - (float)cj - 0.5f)) * dx;
-  const float t = fminf(dd / P.band, 1.f);
+  const float t = fminf(dd * P.inv_band, 1.f);
   const float s = t * t * (3.f - 2.f * t);
   const float uu = W.fx0 + (float)ci * P.ratio, vv = W.fy0 + (float)cj * P.ratio;
   const float fu = floorf(uu), fv = floorf(vv);
@@ -129,35 +124,33 @@ __device__ __forceinline__ void blend_store(const Dev &d, const PatchDev &P, con
 }  // namespace
 
 // ---------------------------------------------------------------- load
-// One wavefront per output tile: weighted count of the particles whose bin
-// origin lies in the tile (every bin belongs to exactly one tile; bins in the
-// margins go to the edge tiles), read from the bin offsets of this step.
+// Relative cost of one particle visit (decode plus footprint work) by path:
+// per-lane atomics with 4 or 8 cells per axis, or the matrix-core quadrants.
+constexpr uint32_t kCostSmall4 = 4, kCostSmall8 = 9, kCostMatrix = 40;
+
+__device__ __forceinline__ uint32_t visit_cost(float rc) {
+  const int span = (int)floorf(2.f * rc) + 1;
+  return span <= 3 ? kCostSmall4 : (span <= 7 ? kCostSmall8 : kCostMatrix);
+}
+
+// One wavefront per output tile: estimated splat cost of the tile, the
+// particles its work items will visit (the bins within 2 r of the tile, per
+// bucket, read from the bin offsets of this step) weighted by visit cost.
 __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) {
   const int t = (int)blockIdx.x * (kThreads / 64) + ((int)threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= nt) return;
   const int tile = t0 + t;
-  const int p = d.tile_patch[tile];
-  const PatchDev &P = d.patches[p];
-  const int lt = tile - P.tile0;
-  const int tx = lt % P.ntx, ty = lt / P.ntx;
-  const int64_t span = (int64_t)kTile * P.dxu;
+  const PatchDev &P = d.patches[d.tile_patch[tile]];
   uint64_t load = 0;
   for (int b = 0; b < d.nb; ++b) {
-    const int64_t m = d.margin[b], binu = P.binu[b];
-    // first bin whose origin (bin * binu - m, window frame) is at or past x
-    auto first_bin = [&](int64_t x) { return (int)((x + m + binu - 1) / binu); };
-    const int bx0 = tx == 0 ? 0 : min(P.nbx[b], first_bin(tx * span));
-    const int bx1 = tx == P.ntx - 1 ? P.nbx[b] : min(P.nbx[b], first_bin((tx + 1) * span));
-    const int by0 = ty == 0 ? 0 : min(P.nby[b], first_bin(ty * span));
-    const int by1 = ty == P.nty - 1 ? P.nby[b] : min(P.nby[b], first_bin((ty + 1) * span));
-    if (bx1 <= bx0) continue;
-    uint32_t cnt = 0;
-    for (int by = by0 + lane; by < by1; by += 64) {
-      const int rb = P.binbase[b] + by * P.nbx[b];
-      cnt += (uint32_t)(d.off[rb + bx1] - d.off[rb + bx0]);
+    const short4 rc = d.tile_rect[(size_t)tile * d.nb + b];
+    uint32_t seen = 0;
+    if (lane < rc.w) {
+      const int rb = P.binbase[b] + (rc.z + lane) * P.nbx[b];
+      seen = (uint32_t)max(0, min(d.off[rb + rc.y + 1], d.cap) - min(d.off[rb + rc.x], d.cap));
     }
-    load += (uint64_t)cnt * d.bcost[b];
+    load += (uint64_t)seen * visit_cost(d.bucket_r[b] / (float)P.dx);
   }
   for (int o = 32; o > 0; o >>= 1) load += __shfl_xor(load, o);
   if (lane == 0) d.tile_load[tile] = (uint32_t)min<uint64_t>(load, 0xFFFFFFFFull);
@@ -168,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) 
 constexpr int kPlanThreads = 1024;
 
 __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int nt, int items_target) {
-  __shared__ uint32_t s_red[kPlanThreads / 64];
+  __shared__ uint64_t s_red[kPlanThreads / 64];
   __shared__ int32_t s_cnt[kPlanThreads / 64];
   __shared__ uint32_t s_chunk;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -178,7 +171,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
   for (int t = beg; t < end; ++t) mine += d.tile_load[t0 + t];
   uint64_t tot = mine;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
-  if (lane == 0) s_red[wv] = (uint32_t)min<uint64_t>(tot, 0xFFFFFFFFull);
+  if (lane == 0) s_red[wv] = tot;
   __syncthreads();
   if (tid == 0) {
     uint64_t all = 0;
@@ -199,7 +192,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
   int32_t cnt = 0;
   for (int t = beg; t < end; ++t) {
     const uint32_t l = d.tile_load[t0 + t];
-    cnt += min(d.max_parts, 1 + (int32_t)(l / chunk));
+    cnt += 1 + (int32_t)(l / chunk);
   }
   // exclusive scan of per-thread counts
   int32_t inc = cnt;
@@ -214,10 +207,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
   int32_t acc = pre + inc - cnt;
   for (int t = beg; t < end; ++t) {
     const uint32_t l = d.tile_load[t0 + t];
-    const int parts = min(d.max_parts, 1 + (int32_t)(l / chunk));
+    const int parts = 1 + (int32_t)(l / chunk);
     d.item_base[t0 + t] = acc;
-    for (int j = 0; j < parts; ++j)
-      d.item_tile[acc + j] = ((uint32_t)(t0 + t) << 12) | ((uint32_t)j << 6) | (uint32_t)(parts - 1);
+    for (int j = 0; j < parts; ++j) d.item_tile[acc + j] = t0 + t;
     acc += parts;
   }
   if (tid == kPlanThreads - 1) {
@@ -230,37 +222,64 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
 constexpr int kChunk = kThreads;   // particles decoded into LDS per step
 constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Small footprints (at most F cells per axis): one crest or trough per lane,
+// weights in registers, LDS float atomics into the tile.  Loops stop as soon
+// as no lane of the wavefront has work left in them.
+template <int F>
+__device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv, bool valid, float rc, float inv_rc,
+                                             int tw, int th) {
+  int ilo = 0, jlo = 0, nc = 0, nr = 0;
+  if (valid && pv.z != 0.f) {
+    ilo = max(0, (int)ceilf(pv.x - rc));
+    jlo = max(0, (int)ceilf(pv.y - rc));
+    nc = min(F, min(tw - 1, (int)floorf(pv.x + rc)) - ilo + 1);
+    nr = min(F, min(th - 1, (int)floorf(pv.y + rc)) - jlo + 1);
+  }
+  float wx[F], wy[F];
+#pragma unroll
+  for (int u = 0; u < F; ++u) {
+    wx[u] = pv.z * wcos(((float)(ilo + u) - pv.x) * inv_rc);
+    wy[u] = wcos(((float)(jlo + u) - pv.y) * inv_rc);
+  }
+#pragma unroll
+  for (int jj = 0; jj < F; ++jj) {
+    if (!__any(jj < nr)) break;
+    float *row = &acc[min(jlo + jj, kTile - 1)][ilo];
+#pragma unroll
+    for (int ii = 0; ii < F; ++ii) {
+      if (!__any(ii < nc)) break;
+      if (jj < nr && ii < nc) atomicAdd(row + ii, wy[jj] * wx[ii]);
+    }
+  }
+}
+
 template <class Rec>
 __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
                                                     int ndirect, float *__restrict__ raw_out,
                                                     float *__restrict__ blend_out, int64_t out_off) {
   __shared__ float acc[kTile][kPad];
-  __shared__ float scratch[kThreads / 64][64];
-  __shared__ float4 wx4[kBatch][kTile / 4];
-  __shared__ float4 wy4[kBatch][kTile / 4];
-  // decoded chunk: crest centre (tile cells), amplitude, direction
-  __shared__ float dc_x[kChunk], dc_y[kChunk], dc_a[kChunk], dc_ux[kChunk], dc_uy[kChunk];
-  __shared__ uint16_t it_idx[2 * kChunk];    // dense items: particle | 0x8000 for the trough
+  // decoded chunk: for particle i of the chunk, pt[2i] is its crest and
+  // pt[2i + 1] its trough: centre (tile cells), signed amplitude (0: skip)
+  __shared__ float4 pt[2 * kChunk];
   // per bucket: bin rows reaching the tile (start, exclusive prefix of lengths)
   __shared__ int s_rlo[kMaxBuckets][kMaxRows];
   __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
   __shared__ int s_nrows[kMaxBuckets];
   __shared__ int s_bstart[kMaxBuckets];      // first index of this part in the bucket's list
   __shared__ int s_boff[kMaxBuckets + 1];    // offsets of the buckets in the item's list
-  __shared__ int s_wcnt[kThreads / 64];
   __shared__ int s_tile, s_part, s_nparts, s_patch;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   constexpr int nwaves = kThreads / 64;
-  float *scr = scratch[wave];
   const int64_t n = d.glob->n;
   const Rec *__restrict__ S = direct ? direct : (const Rec *)((n & 1) ? d.S1 : d.S0);
   const int total = direct ? nt : d.splat_ctl[1];
   const int nb = d.nb;
-  // dense-path ownership: 4x4 cells per thread, wave w owns rows 16w..16w+15
-  const int dc0 = 4 * (lane & 15);
-  const int dr0 = 16 * wave + 4 * (lane >> 4);
+  // matrix-core path: wavefront w owns the 32 x 32 quadrant (xq, yq) of the tile
+  const int xq = 32 * (wave & 1), yq = 32 * (wave >> 1);
 
   for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
     if (tid == 0) {
@@ -270,10 +289,10 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
         part = 0;
         np_ = 1;
       } else {
-        const uint32_t e = d.item_tile[item];
-        tile = (int)(e >> 12);
-        part = (int)((e >> 6) & 63);
-        np_ = (int)(e & 63) + 1;
+        tile = d.item_tile[item];
+        const int base = d.item_base[tile];
+        part = item - base;
+        np_ = d.item_base[tile + 1] - base;
       }
       s_tile = tile;
       s_part = part;
@@ -286,10 +305,6 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
     TileGeom T;
     tile_geom(d, tile, s_patch, T);
     const PatchDev &P = d.patches[T.p];
-    const int32_t dxu = P.dxu;
-    const int64_t ax0 = (int64_t)T.i0 * dxu + dxu / 2;
-    const int64_t ay0 = (int64_t)T.j0 * dxu + dxu / 2;
-
     // ---- row tables of every bucket, loaded in one pass
     for (int q = tid; q < nb * kMaxRows; q += kThreads) {
       const int b = q / kMaxRows, r = q % kMaxRows;
@@ -298,17 +313,12 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
         nrows = 1;
         if (r == 0) len = ndirect;
       } else {
-        const int32_t m = d.margin[b];
-        const int32_t binu = P.binu[b];
-        const int bx_lo = (int)(ax0 / binu);
-        const int bx_hi = min(P.nbx[b] - 1, (int)((ax0 + (int64_t)(T.tw - 1) * dxu + 2 * (int64_t)m) / binu));
-        const int by_lo = (int)(ay0 / binu);
-        const int by_hi = min(P.nby[b] - 1, (int)((ay0 + (int64_t)(T.th - 1) * dxu + 2 * (int64_t)m) / binu));
-        nrows = (bx_lo <= bx_hi && by_lo <= by_hi) ? min(by_hi - by_lo + 1, kMaxRows) : 0;
+        const short4 rc4 = d.tile_rect[(size_t)tile * nb + b];
+        nrows = rc4.w;
         if (r < nrows) {
-          const int rb = P.binbase[b] + (by_lo + r) * P.nbx[b];
-          lo = min(d.off[rb + bx_lo], d.cap);
-          len = max(0, min(d.off[rb + bx_hi + 1], d.cap) - lo);
+          const int rb = P.binbase[b] + (rc4.z + r) * P.nbx[b];
+          lo = min(d.off[rb + rc4.x], d.cap);
+          len = max(0, min(d.off[rb + rc4.y + 1], d.cap) - lo);
         }
       }
       if (r < nrows) {
@@ -344,11 +354,10 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
     }
     __syncthreads();
     const int Mi = s_boff[nb];
-    float racc[4][4];
+    const bool quad_live = xq < T.tw && yq < T.th;
+    f32x16 cq;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) racc[i][j] = 0.f;
+    for (int r = 0; r < 16; ++r) cq[r] = 0.f;
 
     for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
       const int m = min(kChunk, Mi - c);
@@ -368,12 +377,10 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
         float2 u = make_float2(0.f, 0.f);
         TileGeom Tb = T;
         Tb.Ab = P.A[b];
-        const bool valid = load_item<Rec>(d, S, k, n, b, Tb, cx, cy, A, u);
-        dc_x[tid] = cx;
-        dc_y[tid] = cy;
-        dc_a[tid] = valid ? A : 0.f;
-        dc_ux[tid] = u.x;
-        dc_uy[tid] = u.y;
+        if (!load_item<Rec>(d, S, k, n, b, Tb, cx, cy, A, u)) A = 0.f;
+        const float rc = d.bucket_r[b] / (float)P.dx;
+        pt[2 * tid] = make_float4(cx, cy, A, 0.f);
+        pt[2 * tid + 1] = make_float4(cx - rc * u.x, cy - rc * u.y, -A, 0.f);
       }
       __syncthreads();
       // ---- the chunk holds runs of consecutive buckets
@@ -382,118 +389,60 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
         if (seg_hi <= seg_lo) continue;   // block-uniform
         const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
         const float inv_rc = 1.f / rc;
-        if (rc < d.dense_rc) {
-          // ---- group scatter: one crest/trough per group of G lanes
-          int need = (int)floorf(2.f * rc) + 1;
-          int lg = 0;
-          while ((1 << lg) < need && lg < 6) ++lg;
-          const int G = 1 << lg, ppw = 64 >> lg;
-          const int grp = lane >> lg, gl = lane & (G - 1);
-          for (int i0 = seg_lo + wave * ppw; i0 < seg_hi; i0 += nwaves * ppw) {
-            const int i = i0 + grp;
-            const bool valid = i < seg_hi && dc_a[i] != 0.f;
-            const float cx = valid ? dc_x[i] : 0.f, cy = valid ? dc_y[i] : 0.f;
-            const float A = valid ? dc_a[i] : 0.f;
-            const float ux = valid ? dc_ux[i] : 0.f, uy = valid ? dc_uy[i] : 0.f;
-#pragma unroll
-            for (int pass = 0; pass < 2; ++pass) {
-              const float ccx = pass ? cx - rc * ux : cx;
-              const float ccy = pass ? cy - rc * uy : cy;
-              const float amp = pass ? -A : A;
-              int nr = 0, nc = 0, ilo = 0, jlo = 0;
-              if (valid) {
-                ilo = max(0, (int)ceilf(ccx - rc));
-                const int ihi = min(T.tw - 1, (int)floorf(ccx + rc));
-                jlo = max(0, (int)ceilf(ccy - rc));
-                const int jhi = min(T.th - 1, (int)floorf(ccy + rc));
-                if (ihi >= ilo && jhi >= jlo) {
-                  nc = ihi - ilo + 1;
-                  nr = jhi - jlo + 1;
-                }
-              }
-              for (int jj = gl; jj < nr; jj += G) scr[grp * G + jj] = wcos(((float)(jlo + jj) - ccy) * inv_rc);
-              wave_fence();
-              for (int ii = gl; ii < nc; ii += G) {
-                const float wxv = amp * wcos(((float)(ilo + ii) - ccx) * inv_rc);
-                float *col = &acc[jlo][ilo + ii];
-                const float *sw = scr + grp * G;
-                int jj = 0;
-                for (; jj + 4 <= nr; jj += 4) {
-                  const float w0 = sw[jj], w1 = sw[jj + 1], w2 = sw[jj + 2], w3 = sw[jj + 3];
-                  atomicAdd(col + (jj + 0) * kPad, wxv * w0);
-                  atomicAdd(col + (jj + 1) * kPad, wxv * w1);
-                  atomicAdd(col + (jj + 2) * kPad, wxv * w2);
-                  atomicAdd(col + (jj + 3) * kPad, wxv * w3);
-                }
-                for (; jj < nr; ++jj) atomicAdd(col + jj * kPad, wxv * sw[jj]);
-              }
-              wave_fence();
+        const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
+        const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
+        if (span <= 7) {
+          // ---- small footprints: points spread over all wavefronts
+          for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
+            const int q = q0 + lane;
+            const bool valid = q < q_hi;
+            const float4 pv = pt[valid ? q : q_lo];
+            if (span <= 3) splat_points<4>(acc, pv, valid, rc, inv_rc, T.tw, T.th);
+            else splat_points<8>(acc, pv, valid, rc, inv_rc, T.tw, T.th);
+          }
+        } else if (quad_live) {
+          // ---- matrix cores: the wavefront's quadrant gets the rank-2 update
+          //      D += W_y(:, k1 k2) [A_k1 W_x(k1, :); A_k2 W_x(k2, :)]
+          //      for each pair of points that reach it
+          const float xlo = (float)xq, ylo = (float)yq;
+          const int mr = lane & 31;
+          for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
+            const int q = q0 + lane;
+            bool hit = false;
+            if (q < q_hi) {
+              const float4 pv = pt[q];
+              hit = pv.z != 0.f && pv.x + rc > xlo && pv.x - rc < xlo + 31.f && pv.y + rc > ylo &&
+                    pv.y - rc < ylo + 31.f;
             }
-          }
-        } else {
-          // ---- dense rank-K update: keep only crests/troughs that overlap the tile
-          int nmine = 0;
-          bool oc = false, ot = false;
-          if (tid >= seg_lo && tid < seg_hi && dc_a[tid] != 0.f) {
-            const float cx = dc_x[tid], cy = dc_y[tid];
-            const float tx = cx - rc * dc_ux[tid], ty = cy - rc * dc_uy[tid];
-            oc = cx + rc >= 0.f && cx - rc <= (float)(T.tw - 1) && cy + rc >= 0.f && cy - rc <= (float)(T.th - 1);
-            ot = tx + rc >= 0.f && tx - rc <= (float)(T.tw - 1) && ty + rc >= 0.f && ty - rc <= (float)(T.th - 1);
-            nmine = (oc ? 1 : 0) + (ot ? 1 : 0);
-          }
-          int inc = nmine;
-          for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
-          }
-          if (lane == 63) s_wcnt[wave] = inc;
-          __syncthreads();
-          int base = 0, nitems = 0;
-          for (int w = 0; w < nwaves; ++w) {
-            if (w < wave) base += s_wcnt[w];
-            nitems += s_wcnt[w];
-          }
-          int pos = base + inc - nmine;
-          if (oc) it_idx[pos++] = (uint16_t)tid;
-          if (ot) it_idx[pos] = (uint16_t)(tid | 0x8000);
-          __syncthreads();
-          for (int ib = 0; ib < nitems; ib += kBatch) {   // block-uniform
-            const int nbatch = min(kBatch, nitems - ib);
-            for (int vv = tid; vv < nbatch * 2 * kTile; vv += kThreads) {
-              const int it = vv / (2 * kTile), which = (vv / kTile) & 1, q = vv % kTile;
-              const int e = it_idx[ib + it], pi = e & 0x7FFF;
-              const bool tr = (e & 0x8000) != 0;
-              if (which == 0) {
-                const float ccx = tr ? dc_x[pi] - rc * dc_ux[pi] : dc_x[pi];
-                const float amp = tr ? -dc_a[pi] : dc_a[pi];
-                reinterpret_cast<float *>(&wx4[it][0])[q] = (q < T.tw) ? amp * wcos(((float)q - ccx) * inv_rc) : 0.f;
-              } else {
-                const float ccy = tr ? dc_y[pi] - rc * dc_uy[pi] : dc_y[pi];
-                reinterpret_cast<float *>(&wy4[it][0])[q] = (q < T.th) ? wcos(((float)q - ccy) * inv_rc) : 0.f;
+            uint64_t mask = __ballot(hit);
+            while (mask) {
+              const int k1 = __builtin_ctzll(mask);
+              mask &= mask - 1;
+              int k2 = k1;
+              float keep = lane < 32 ? 1.f : 0.f;
+              if (mask) {
+                k2 = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                keep = 1.f;
               }
+              const float4 pv = pt[q0 + (lane < 32 ? k1 : k2)];
+              const float a = wcos(((float)(yq + mr) - pv.y) * inv_rc);
+              const float bw = keep * pv.z * wcos(((float)(xq + mr) - pv.x) * inv_rc);
+              cq = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bw, cq, 0, 0, 0);
             }
-            __syncthreads();
-            for (int it = 0; it < nbatch; ++it) {
-              const float4 yv = wy4[it][dr0 >> 2];
-              if (yv.x == 0.f && yv.y == 0.f && yv.z == 0.f && yv.w == 0.f) continue;
-              const float4 xv = wx4[it][dc0 >> 2];
-              const float xs[4] = {xv.x, xv.y, xv.z, xv.w};
-              const float ys[4] = {yv.x, yv.y, yv.z, yv.w};
-#pragma unroll
-              for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) racc[i][j] = fmaf(ys[i], xs[j], racc[i][j]);
-            }
-            __syncthreads();
           }
         }
       }
       __syncthreads();
     }
+    // ---- matrix-core quadrants into the tile (disjoint per wavefront)
+    if (quad_live) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[dr0 + i][dc0 + j] += racc[i][j];
+      for (int r = 0; r < 16; ++r) {
+        const int row = yq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        acc[row][xq + (lane & 31)] += cq[r];
+      }
+    }
     __syncthreads();
 
     if (nparts == 1) {
