@@ -156,9 +156,19 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * launch with HIP events (graph replay is then disabled); hwo_stage_times
  * returns accumulated milliseconds and launch counts per stage:
  *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat
- *   7 splat_plan  8 splat_reduce  (n >= 9) */
+ *   7 splat_plan  8 splat_reduce  9 bin_plan (n >= 10).  bin_plan is the
+ *   one-block scan + tile estimates + plan that replaces stages 4 and 7 in
+ *   the batched form of scenes with at most 65536 bins and 4096 tiles. */
 int hwo_set_timing(hwo_ocean *o, int32_t enable);
 int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
+/* Benchmark support: after at least one step, launch the kernels of one
+ * stage reps times back to back between two HIP events on the library stream
+ * and store the mean milliseconds per repetition (all launch groups of the
+ * stage).  Only stages whose kernels are idempotent for a finished frame are
+ * accepted: 1 fft_a, 2 fft_b, 6 splat, 7 splat_plan, 8 splat_reduce; any other
+ * stage gives HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are
+ * rewritten with the same values (up to FP32 summation order). */
+int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep);
 /* Bytes of particle storage per record for the active form (16 or 32). */
 int32_t hwo_record_bytes(const hwo_ocean *o);
 

@@ -150,7 +150,8 @@ struct Dev {
   int32_t *item_tile;          // [max_items] tile of each work item (plan)
   const int32_t *tile_patch;   // [ntiles] patch of each output tile
   const short4 *tile_rect;     // [ntiles][nb] bins reaching the tile: bx_lo, bx_hi, by_lo, nrows
-  int32_t *splat_ctl;          // [0] next item, [1] total items
+  int32_t *splat_ctl;          // [1] total items, [2] split tiles (plan)
+  int32_t *split_tiles;        // [ntiles] tiles with more than one part (plan)
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
   int32_t max_items;           // capacity of partials (items)
   uint32_t chunk_load;         // target load per work item
@@ -195,8 +196,8 @@ __device__ inline int64_t cum_count(uint64_t R, int64_t n) {
 template <class Rec> struct RecIO;
 
 template <> struct RecIO<RecWide> {
-  __device__ static Part load(const RecWide *S, int64_t i, int64_t n) {
-    RecWide r = S[i];
+  __device__ static Part load(const RecWide *S, int64_t i, int64_t n) { return unpack(S[i], n); }
+  __device__ static Part unpack(const RecWide &r, int64_t n) {
     Part p;
     p.ox = r.ox; p.oy = r.oy; p.code = r.code; p.meta = r.meta; p.amp = r.amp;
     p.age = (int32_t)(n - (int64_t)r.birth);
@@ -212,8 +213,8 @@ template <> struct RecIO<RecWide> {
 };
 
 template <> struct RecIO<RecCompact> {
-  __device__ static Part load(const RecCompact *S, int64_t i, int64_t n) {
-    RecCompact r = S[i];
+  __device__ static Part load(const RecCompact *S, int64_t i, int64_t n) { return unpack(S[i], n); }
+  __device__ static Part unpack(const RecCompact &r, int64_t n) {
     Part p;
     p.ox = r.ox; p.oy = r.oy; p.code = (int32_t)(r.bc >> 16); p.meta = r.meta; p.amp = 0.f;
     uint32_t a = ((uint32_t)n - (r.bc & 0xFFFFu)) & 0xFFFFu;
@@ -252,6 +253,9 @@ void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStre
 void launch_scan(const Dev &d, int bin_lo, int bin_hi, bool first, bool last, hipStream_t st);
 void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipStream_t st);
 void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st);
+// Fused scan + tile estimates + plan for a whole small scene (one block).
+bool bin_plan_fits(int nbins, int ntiles);
+void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipStream_t st);
 void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st);
 void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw,
                          int64_t out_off, hipStream_t st);

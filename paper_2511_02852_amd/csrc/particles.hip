@@ -203,6 +203,23 @@ __device__ __forceinline__ Run wave_runs(int32_t key) {
   return r;
 }
 
+// Add inc to counter ctr[key] for every lane with key >= 0: one atomic per
+// distinct key in the wavefront (lanes of a wavefront nearly always share
+// their patch and bucket, so this is usually a single atomic).
+__device__ __forceinline__ void wave_add(unsigned long long *ctr, int key, uint32_t inc) {
+  uint64_t act = __ballot(key >= 0);
+  while (act) {
+    const int leader = __builtin_ctzll(act);
+    const int lk = __shfl(key, leader);
+    const bool mine = key == lk;
+    const uint64_t same = __ballot(mine);
+    uint32_t v = mine ? inc : 0u;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((int)__lane_id() == leader) atomicAdd(&ctr[lk], (unsigned long long)v);
+    act &= ~same;
+  }
+}
+
 template <class Rec, bool kScatter>
 __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   const int64_t n = d.glob->n;
@@ -221,6 +238,8 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
     int32_t key[3] = {-1, -1, -1};
     int nout = 0;
     int pid = 0, bkt = 0;
+    bool subdivided = false;
+    uint32_t ndead = 0;
     if (k < nex) {
       // ---- a previous particle: subdivide, then survive
       Part q = RecIO<Rec>::load(Sin, ex0 + k, n);
@@ -242,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
           o[1].code = (q.code - off + kNCode) % kNCode;
           o[2].code = (q.code + off) % kNCode;
           nout = 3;
-          if (!kScatter) atomicAdd(&d.ctr[((size_t)pid * d.nb + bkt) * CNT_NUM + CNT_SUB], 1ull);
+          subdivided = true;
         }
       }
     } else if (k < nex + ninj) {
@@ -314,9 +333,13 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       for (int r = 0; r < nout; ++r) {
         int64_t px, py;
         key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age, px, py);
-        if (!kScatter && key[r] < 0)
-          atomicAdd(&d.ctr[((size_t)pid * d.nb + bkt) * CNT_NUM + CNT_DIED], 1ull);
+        if (key[r] < 0) ++ndead;
       }
+    }
+    if (!kScatter) {
+      const int cbase = (pid * d.nb + bkt) * CNT_NUM;
+      wave_add(d.ctr, subdivided ? cbase + CNT_SUB : -1, 1u);
+      wave_add(d.ctr, ndead ? cbase + CNT_DIED : -1, ndead);
     }
     // merge runs of equal keys, one atomic per run
 #pragma unroll

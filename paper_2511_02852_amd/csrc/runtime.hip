@@ -33,8 +33,8 @@ namespace {
 constexpr double kUnit = 1048576.0;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kTwo30 = 1073741824.0;
-constexpr int kStages = 9;
-enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE };
+constexpr int kStages = 10;
+enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE, ST_BINPLAN };
 
 int64_t pmod(int64_t a, int64_t m) {
   int64_t r = a % m;
@@ -84,9 +84,15 @@ struct hwo_ocean {
   uint32_t *cdf = nullptr, *cdfQ = nullptr;
   int update_grid = 1024;
   int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
-  int items_target = 2048;          // splat work items per frame the plan aims for (beyond one per tile)
+  int items_target = 4096;          // splat work items per frame the plan aims for (beyond one per tile)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // batched form: the background FFT runs on a second branch of the frame
+  // graph, joined before the splat (which blends with it)
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool capturing = false;
+  bool fused = false;              // one-block scan + estimates + plan (small scenes)
   // timing
   bool timing = false;
   std::vector<TimedLaunch> tl;
@@ -177,6 +183,9 @@ void hwo_destroy_ocean(hwo_ocean *o) {
   if (o->st) (void)hipStreamSynchronize(o->st);
   if (o->exec) (void)hipGraphExecDestroy(o->exec);
   if (o->graph) (void)hipGraphDestroy(o->graph);
+  if (o->ev_fork) (void)hipEventDestroy(o->ev_fork);
+  if (o->ev_join) (void)hipEventDestroy(o->ev_join);
+  if (o->st2) (void)hipStreamDestroy(o->st2);
   for (auto &t : o->tl) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);
@@ -560,10 +569,11 @@ static int finalize(hwo_ocean *o) {
   d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   // splat work plan
   d.max_items = d.ntiles + 4096;
-  d.chunk_load = 256;
+  d.chunk_load = 6000;   // least estimated cost per work item (about 400 particle visits)
   d.tile_load = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
   d.item_base = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.ntiles + 1));
-  d.splat_ctl = (int32_t *)o->alloc(sizeof(int32_t) * 2);
+  d.splat_ctl = (int32_t *)o->alloc(sizeof(int32_t) * 4);
+  d.split_tiles = (int32_t *)o->alloc(sizeof(int32_t) * (size_t)std::max(d.ntiles, 1));
   d.item_tile = (int32_t *)o->alloc(sizeof(int32_t) * (size_t)d.max_items);
   {
     std::vector<int32_t> tp((size_t)std::max(d.ntiles, 1), 0);
@@ -598,7 +608,7 @@ static int finalize(hwo_ocean *o) {
   }
   if (!d.item_tile) return o->fail(HWO_ENOMEM, "device allocation failed");
   d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
-  if (!d.tile_load || !d.item_base || !d.splat_ctl || !d.partials)
+  if (!d.tile_load || !d.item_base || !d.splat_ctl || !d.split_tiles || !d.partials)
     return o->fail(HWO_ENOMEM, "device allocation failed");
   if (!d.glob || !d.sp || !d.inj_off || !d.em_off || !d.src_pos || !d.ctr || !d.hist || !d.off || !d.cur ||
       !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
@@ -613,33 +623,24 @@ static int finalize(hwo_ocean *o) {
   HWO_CHECK(hipMemsetAsync(d.H, 0, sizeof(float) * (size_t)N * N, o->st));
   HWO_CHECK(hipMemsetAsync(d.tile_load, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.item_base, 0, sizeof(int32_t) * ((size_t)d.ntiles + 1), o->st));
-  HWO_CHECK(hipMemsetAsync(d.splat_ctl, 0, sizeof(int32_t) * 2, o->st));
+  HWO_CHECK(hipMemsetAsync(d.splat_ctl, 0, sizeof(int32_t) * 4, o->st));
   HWO_CHECK(hipStreamSynchronize(o->st));
   int dev_id = 0, cus = 256;
   (void)hipGetDevice(&dev_id);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
   o->update_grid = std::max(64, 4 * cus);
   o->target_blocks = std::max(64, 4 * cus);
+  if (o->cfg.batched) {
+    o->fused = bin_plan_fits(d.nbins, d.ntiles);
+    HWO_CHECK(hipStreamCreateWithFlags(&o->st2, hipStreamNonBlocking));
+    HWO_CHECK(hipEventCreateWithFlags(&o->ev_fork, hipEventDisableTiming));
+    HWO_CHECK(hipEventCreateWithFlags(&o->ev_join, hipEventDisableTiming));
+  }
   o->finalized = true;
   return HWO_OK;
 }
 
 // ---------------------------------------------------------------- stepping
-static void timed(hwo_ocean *o, int stage, void (*fn)(hwo_ocean *, void *), void *arg) {
-  if (!o->timing) {
-    fn(o, arg);
-    return;
-  }
-  TimedLaunch t;
-  t.stage = stage;
-  (void)hipEventCreate(&t.a);
-  (void)hipEventCreate(&t.b);
-  (void)hipEventRecord(t.a, o->st);
-  fn(o, arg);
-  (void)hipEventRecord(t.b, o->st);
-  o->tl.push_back(t);
-}
-
 struct PatchArg {
   int p0, p1;     // patch range
   int b0, b1;     // bin range
@@ -647,13 +648,44 @@ struct PatchArg {
   int t0, t1;     // output tile range
 };
 
-static void run_step(hwo_ocean *o) {
-  Dev &d = o->dev;
-  hipStream_t st = o->st;
-  timed(o, ST_PARAMS, [](hwo_ocean *oo, void *) { launch_params(oo->dev, oo->st); }, nullptr);
-  timed(o, ST_FFT_A, [](hwo_ocean *oo, void *) { launch_fft_a(oo->dev, oo->st); }, nullptr);
-  timed(o, ST_FFT_B, [](hwo_ocean *oo, void *) { launch_fft_b(oo->dev, oo->st); }, nullptr);
-  if (d.np == 0) return;
+// Launch the kernels of one stage (for one launch group of patches).
+static void launch_stage(hwo_ocean *o, int stage, const PatchArg *g) {
+  const Dev &d = o->dev;
+  switch (stage) {
+    case ST_PARAMS: launch_params(d, o->st); break;
+    case ST_FFT_A: launch_fft_a(d, o->st); break;
+    case ST_FFT_B: launch_fft_b(d, o->st); break;
+    case ST_COUNT: launch_update(d, g->p0, g->p1, false, o->update_grid, o->st); break;
+    case ST_SCAN: launch_scan(d, g->b0, g->b1, g->first, g->last, o->st); break;
+    case ST_SCATTER: launch_update(d, g->p0, g->p1, true, o->update_grid, o->st); break;
+    case ST_PLAN: launch_splat_plan(d, g->t0, g->t1 - g->t0, o->items_target, o->st); break;
+    case ST_SPLAT:
+      launch_splat_tiles(d, g->t0, g->t1 - g->t0, std::max(1, std::min(4 * o->target_blocks, d.max_items)), o->st);
+      break;
+    case ST_REDUCE: launch_splat_reduce(d, g->t0, g->t1 - g->t0, o->st); break;
+    case ST_BINPLAN: launch_bin_plan(d, d.nbins, d.ntiles, o->items_target, o->st); break;
+    default: break;
+  }
+}
+
+static void timed(hwo_ocean *o, int stage, const PatchArg *g) {
+  if (!o->timing) {
+    launch_stage(o, stage, g);
+    return;
+  }
+  TimedLaunch t;
+  t.stage = stage;
+  (void)hipEventCreate(&t.a);
+  (void)hipEventCreate(&t.b);
+  (void)hipEventRecord(t.a, o->st);
+  launch_stage(o, stage, g);
+  (void)hipEventRecord(t.b, o->st);
+  o->tl.push_back(t);
+}
+
+// Launch groups: the whole ocean (batched) or one group per patch.
+static std::vector<PatchArg> launch_groups(const hwo_ocean *o) {
+  const Dev &d = o->dev;
   std::vector<PatchArg> groups;
   if (o->cfg.batched) {
     groups.push_back({0, d.np, 0, d.nbins, true, true, 0, 0});
@@ -662,40 +694,59 @@ static void run_step(hwo_ocean *o) {
       groups.push_back({p, p + 1, o->pdev[p].bin_lo, o->pdev[p].bin_hi, p == 0, p == d.np - 1, 0, 0});
   }
   for (auto &gp : groups) {
-    timed(o, ST_COUNT, [](hwo_ocean *oo, void *a) {
-      auto *g = (PatchArg *)a;
-      launch_update(oo->dev, g->p0, g->p1, false, oo->update_grid, oo->st);
-    }, &gp);
-    timed(o, ST_SCAN, [](hwo_ocean *oo, void *a) {
-      auto *g = (PatchArg *)a;
-      launch_scan(oo->dev, g->b0, g->b1, g->first, g->last, oo->st);
-    }, &gp);
-    timed(o, ST_SCATTER, [](hwo_ocean *oo, void *a) {
-      auto *g = (PatchArg *)a;
-      launch_update(oo->dev, g->p0, g->p1, true, oo->update_grid, oo->st);
-    }, &gp);
-  }
-  for (auto &gp : groups) {
     const PatchDev &P0 = o->pdev[gp.p0];
     const PatchDev &P1 = o->pdev[gp.p1 - 1];
     gp.t0 = P0.tile0;
     gp.t1 = P1.tile0 + P1.ntx * P1.nty;
-    timed(o, ST_PLAN, [](hwo_ocean *oo, void *a) {
-      auto *g = (PatchArg *)a;
-      launch_splat_plan(oo->dev, g->t0, g->t1 - g->t0, oo->items_target, oo->st);
-    }, &gp);
-    timed(o, ST_SPLAT, [](hwo_ocean *oo, void *a) {
-      auto *g = (PatchArg *)a;
-      const int nt = g->t1 - g->t0;
-      const int grid = std::max(1, std::min(4 * oo->target_blocks, oo->dev.max_items));
-      launch_splat_tiles(oo->dev, g->t0, nt, grid, oo->st);
-    }, &gp);
-    timed(o, ST_REDUCE, [](hwo_ocean *oo, void *a) {
-      auto *g = (PatchArg *)a;
-      launch_splat_reduce(oo->dev, g->t0, g->t1 - g->t0, oo->st);
-    }, &gp);
   }
-  (void)st;
+  return groups;
+}
+
+static void run_step(hwo_ocean *o) {
+  // While a frame graph is captured the FFT forks onto st2 after the step
+  // parameters (it needs the step index) and joins before the first splat.
+  const bool fork = o->capturing && o->st2;
+  timed(o, ST_PARAMS, nullptr);
+  if (fork) {
+    (void)hipEventRecord(o->ev_fork, o->st);
+    (void)hipStreamWaitEvent(o->st2, o->ev_fork, 0);
+    launch_fft_a(o->dev, o->st2);
+    launch_fft_b(o->dev, o->st2);
+    (void)hipEventRecord(o->ev_join, o->st2);
+  } else {
+    timed(o, ST_FFT_A, nullptr);
+    timed(o, ST_FFT_B, nullptr);
+  }
+  bool joined = !fork;
+  auto join = [&]() {
+    if (!joined) (void)hipStreamWaitEvent(o->st, o->ev_join, 0);
+    joined = true;
+  };
+  if (o->dev.np > 0) {
+    const std::vector<PatchArg> groups = launch_groups(o);
+    if (o->fused) {
+      // one group: the plan needs only the bin offsets, so it precedes the scatter
+      timed(o, ST_COUNT, &groups[0]);
+      timed(o, ST_BINPLAN, &groups[0]);
+      timed(o, ST_SCATTER, &groups[0]);
+      join();
+      timed(o, ST_SPLAT, &groups[0]);
+      timed(o, ST_REDUCE, &groups[0]);
+    } else {
+      for (const auto &gp : groups) {
+        timed(o, ST_COUNT, &gp);
+        timed(o, ST_SCAN, &gp);
+        timed(o, ST_SCATTER, &gp);
+      }
+      for (const auto &gp : groups) {
+        timed(o, ST_PLAN, &gp);
+        join();
+        timed(o, ST_SPLAT, &gp);
+        timed(o, ST_REDUCE, &gp);
+      }
+    }
+  }
+  join();
 }
 
 static int collect_timing(hwo_ocean *o) {
@@ -726,7 +777,9 @@ int hwo_step(hwo_ocean *o, int32_t nsteps) {
     if (use_graph) {
       if (!o->exec) {
         HWO_CHECK(hipStreamBeginCapture(o->st, hipStreamCaptureModeThreadLocal));
+        o->capturing = true;
         run_step(o);
+        o->capturing = false;
         HWO_CHECK(hipStreamEndCapture(o->st, &o->graph));
         HWO_CHECK(hipGraphInstantiate(&o->exec, o->graph, nullptr, nullptr, 0));
       }
@@ -960,6 +1013,34 @@ int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n) {
     ms[s] = o->stage_ms[s];
     launches[s] = o->stage_n[s];
   }
+  return HWO_OK;
+}
+
+int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep) {
+  if (!o || !ms_per_rep || reps < 1) return HWO_EINVAL;
+  if (stage != ST_FFT_A && stage != ST_FFT_B && stage != ST_PLAN && stage != ST_SPLAT && stage != ST_REDUCE)
+    return o->fail(HWO_EINVAL, "stage is not repeatable (it advances or consumes state)");
+  if (o->n_host < 1) return o->fail(HWO_ESTATE, "time_stage needs a completed step");
+  int rc = collect_timing(o);
+  if (rc) return rc;
+  const std::vector<PatchArg> groups = launch_groups(o);
+  hipEvent_t a = nullptr, b = nullptr;
+  HWO_CHECK(hipEventCreate(&a));
+  HWO_CHECK(hipEventCreate(&b));
+  HWO_CHECK(hipEventRecord(a, o->st));
+  for (int k = 0; k < reps; ++k) {
+    if (stage == ST_FFT_A || stage == ST_FFT_B) launch_stage(o, stage, nullptr);
+    else
+      for (const auto &gp : groups) launch_stage(o, stage, &gp);
+  }
+  HWO_CHECK(hipEventRecord(b, o->st));
+  HWO_CHECK(hipEventSynchronize(b));
+  float ms = 0.f;
+  HWO_CHECK(hipEventElapsedTime(&ms, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  HWO_CHECK(hipGetLastError());
+  *ms_per_rep = (double)ms / reps;
   return HWO_OK;
 }
 

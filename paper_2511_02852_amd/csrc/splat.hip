@@ -54,11 +54,11 @@ struct TileGeom {
   float inv_dxu;
 };
 
-// Decode particle k: crest centre in tile cell coordinates, amplitude, direction.
+// Decode a particle record: crest centre in tile cell coordinates, amplitude, direction.
 template <class Rec>
-__device__ __forceinline__ bool load_item(const Dev &d, const Rec *__restrict__ S, int k, int64_t n, int b,
-                                          const TileGeom &T, float &cx, float &cy, float &A, float2 &u) {
-  const Part q = RecIO<Rec>::load(S, k, n);
+__device__ __forceinline__ bool load_item(const Dev &d, const Rec &r, int64_t n, int b, const TileGeom &T, float &cx,
+                                          float &cy, float &A, float2 &u) {
+  const Part q = RecIO<Rec>::unpack(r, n);
   if ((int)m_bucket(q.meta) != b || (int)m_patch(q.meta) != T.p) return false;
   const int2 v = d.V[b * kNCode + q.code];
   const int64_t px = (int64_t)q.ox + (((int64_t)q.age * v.x) >> 12);
@@ -159,16 +159,24 @@ __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) 
 // ---------------------------------------------------------------- plan
 // One block: parts per tile from the loads, prefix of work items.
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanLdsTiles = 8192;   // tiles whose item prefix fits in LDS for the parallel fill
+constexpr int kFusedMaxTiles = 4096;  // tiles of a scene that k_bin_plan handles
+constexpr int kFusedMaxBins = 65536;  // bins of a scene that k_bin_plan handles
 
-__global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int nt, int items_target) {
+// Body of the plan, run by one block of kPlanThreads threads; load[t] is the
+// cost estimate of tile t0 + t (global memory or LDS).
+__device__ void plan_items(const Dev &d, int t0, int nt, int items_target, const uint32_t *load) {
   __shared__ uint64_t s_red[kPlanThreads / 64];
   __shared__ int32_t s_cnt[kPlanThreads / 64];
+  __shared__ int32_t s_nsp[kPlanThreads / 64];
   __shared__ uint32_t s_chunk;
+  __shared__ int32_t s_base[kPlanLdsTiles];
+  __shared__ int32_t s_total;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int per = (nt + kPlanThreads - 1) / kPlanThreads;
   const int beg = tid * per, end = min(nt, beg + per);
   uint64_t mine = 0;
-  for (int t = beg; t < end; ++t) mine += d.tile_load[t0 + t];
+  for (int t = beg; t < end; ++t) mine += load[t];
   uint64_t tot = mine;
   for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
   if (lane == 0) s_red[wv] = tot;
@@ -189,33 +197,117 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
   }
   __syncthreads();
   const uint32_t chunk = s_chunk;
-  int32_t cnt = 0;
+  int32_t cnt = 0, nsp = 0;   // items and split tiles of this thread's tiles
   for (int t = beg; t < end; ++t) {
-    const uint32_t l = d.tile_load[t0 + t];
+    const uint32_t l = load[t];
     cnt += 1 + (int32_t)(l / chunk);
+    nsp += l >= chunk ? 1 : 0;
   }
-  // exclusive scan of per-thread counts
-  int32_t inc = cnt;
+  // exclusive scans of the per-thread counts
+  int32_t inc = cnt, inc_s = nsp;
   for (int o = 1; o < 64; o <<= 1) {
-    const int32_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
+    const int32_t y = __shfl_up(inc, o), ys = __shfl_up(inc_s, o);
+    if (lane >= o) {
+      inc += y;
+      inc_s += ys;
+    }
   }
-  if (lane == 63) s_cnt[wv] = inc;
+  if (lane == 63) {
+    s_cnt[wv] = inc;
+    s_nsp[wv] = inc_s;
+  }
   __syncthreads();
-  int32_t pre = 0;
-  for (int w = 0; w < wv; ++w) pre += s_cnt[w];
-  int32_t acc = pre + inc - cnt;
+  int32_t pre = 0, pre_s = 0;
+  for (int w = 0; w < wv; ++w) {
+    pre += s_cnt[w];
+    pre_s += s_nsp[w];
+  }
+  int32_t acc = pre + inc - cnt, sp = pre_s + inc_s - nsp;
+  const bool in_lds = nt <= kPlanLdsTiles;
   for (int t = beg; t < end; ++t) {
-    const uint32_t l = d.tile_load[t0 + t];
+    const uint32_t l = load[t];
     const int parts = 1 + (int32_t)(l / chunk);
     d.item_base[t0 + t] = acc;
-    for (int j = 0; j < parts; ++j) d.item_tile[acc + j] = t0 + t;
+    if (parts > 1) d.split_tiles[sp++] = t0 + t;
+    if (in_lds) s_base[t] = acc;
+    else
+      for (int j = 0; j < parts; ++j) d.item_tile[acc + j] = t0 + t;
     acc += parts;
   }
   if (tid == kPlanThreads - 1) {
     d.item_base[t0 + nt] = acc;
     d.splat_ctl[1] = acc;
+    d.splat_ctl[2] = sp;
+    s_total = acc;
   }
+  if (!in_lds) return;
+  __syncthreads();
+  // every thread fills items: tile = last tile whose first item is <= item
+  const int total = s_total;
+  for (int it = tid; it < total; it += kPlanThreads) {
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_base[mid] <= it) lo = mid; else hi = mid - 1;
+    }
+    d.item_tile[it] = t0 + lo;
+  }
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int nt, int items_target) {
+  plan_items(d, t0, nt, items_target, d.tile_load + t0);
+}
+
+// Small scenes, one block: exclusive scan of the bin histogram (offsets,
+// cursors, cleared histogram, totals), then the cost estimate of every tile
+// from the new offsets, then the plan.  Replaces the two scan launches, the
+// load launch and the plan launch when all bins and tiles fit one block.
+__global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int nt, int items_target) {
+  __shared__ uint32_t s_load[kFusedMaxTiles];
+  __shared__ int32_t s_w[kPlanThreads / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // ---- scan: each thread a run of consecutive bins
+  const int per = (nbins + kPlanThreads - 1) / kPlanThreads;
+  const int beg = min(nbins, tid * per), end = min(nbins, beg + per);
+  int32_t sum = 0;
+  for (int i = beg; i < end; ++i) sum += d.hist[i];
+  int32_t inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) s_w[wv] = inc;
+  for (int t = tid; t < nt; t += kPlanThreads) s_load[t] = 0;
+  __syncthreads();
+  int32_t acc = inc - sum;
+  for (int w = 0; w < wv; ++w) acc += s_w[w];
+  for (int i = beg; i < end; ++i) {
+    const int32_t v = d.hist[i];
+    d.off[i] = acc;
+    d.cur[i] = acc;
+    d.hist[i] = 0;
+    acc += v;
+  }
+  if (tid == kPlanThreads - 1) {
+    d.off[nbins] = acc;
+    d.glob->total = acc;
+    d.glob->n_live = min(acc, d.cap);
+  }
+  __syncthreads();
+  // ---- tile cost estimates: one (tile, bucket) pair per thread
+  for (int q = tid; q < nt * d.nb; q += kPlanThreads) {
+    const int t = q / d.nb, b = q % d.nb;
+    const PatchDev &P = d.patches[d.tile_patch[t]];
+    const short4 rc = d.tile_rect[(size_t)t * d.nb + b];
+    uint32_t seen = 0;
+    for (int r = 0; r < rc.w; ++r) {
+      const int rb = P.binbase[b] + (rc.z + r) * P.nbx[b];
+      seen += (uint32_t)max(0, min(d.off[rb + rc.y + 1], d.cap) - min(d.off[rb + rc.x], d.cap));
+    }
+    if (seen) atomicAdd(&s_load[t], seen * visit_cost(d.bucket_r[b] / (float)P.dx));
+  }
+  __syncthreads();
+  plan_items(d, 0, nt, items_target, s_load);
 }
 
 // ---------------------------------------------------------------- splat
@@ -240,8 +332,10 @@ __device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv
   float wx[F], wy[F];
 #pragma unroll
   for (int u = 0; u < F; ++u) {
-    wx[u] = pv.z * wcos(((float)(ilo + u) - pv.x) * inv_rc);
-    wy[u] = wcos(((float)(jlo + u) - pv.y) * inv_rc);
+    wx[u] = 0.f;
+    wy[u] = 0.f;
+    if (__any(u < nc)) wx[u] = pv.z * wcos(((float)(ilo + u) - pv.x) * inv_rc);
+    if (__any(u < nr)) wy[u] = wcos(((float)(jlo + u) - pv.y) * inv_rc);
   }
 #pragma unroll
   for (int jj = 0; jj < F; ++jj) {
@@ -359,10 +453,13 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
 #pragma unroll
     for (int r = 0; r < 16; ++r) cq[r] = 0.f;
 
-    for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
-      const int m = min(kChunk, Mi - c);
-      // ---- decode: item-list index -> bucket -> bin row -> particle (one per thread)
-      if (tid < m) {
+    // The records of chunk c + 1 are loaded while chunk c is splatted.
+    Rec rec;
+    int rec_b = -1;   // bucket of the prefetched record, -1: none
+    auto fetch = [&](int c) {
+      rec_b = -1;
+      if (tid < min(kChunk, Mi - c)) {
+        // item-list index -> bucket -> bin row -> particle
         const int g = c + tid;
         int b = 0;
         while (b + 1 < nb && s_boff[b + 1] <= g) ++b;
@@ -372,17 +469,27 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
           const int mid = (lo + hi + 1) >> 1;
           if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
         }
-        const int k = s_rlo[b][lo] + (v - s_pre[b][lo]);
+        rec = S[s_rlo[b][lo] + (v - s_pre[b][lo])];
+        rec_b = b;
+      }
+    };
+    fetch(0);
+    for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
+      const int m = min(kChunk, Mi - c);
+      // ---- decode the prefetched records into crest and trough points
+      if (rec_b >= 0) {
+        const int b = rec_b;
         float cx = 0.f, cy = 0.f, A = 0.f;
         float2 u = make_float2(0.f, 0.f);
         TileGeom Tb = T;
         Tb.Ab = P.A[b];
-        if (!load_item<Rec>(d, S, k, n, b, Tb, cx, cy, A, u)) A = 0.f;
+        if (!load_item<Rec>(d, rec, n, b, Tb, cx, cy, A, u)) A = 0.f;
         const float rc = d.bucket_r[b] / (float)P.dx;
         pt[2 * tid] = make_float4(cx, cy, A, 0.f);
         pt[2 * tid + 1] = make_float4(cx - rc * u.x, cy - rc * u.y, -A, 0.f);
       }
       __syncthreads();
+      if (c + kChunk < Mi) fetch(c + kChunk);
       // ---- the chunk holds runs of consecutive buckets
       for (int b = 0; b < nb; ++b) {
         const int seg_lo = max(c, s_boff[b]) - c, seg_hi = min(c + m, s_boff[b + 1]) - c;
@@ -460,32 +567,56 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
 }
 
 // ---------------------------------------------------------------- reduce
-// Block (tile, stripe of 4 rows): sums the partial tiles of a split tile and
-// runs the blend.  Tiles with a single part were finished by k_splat.
+// Persistent grid over the units (split tile, stripe of 4 rows) listed by the
+// plan: sums the partial tiles of the split tile and runs the blend.  Tiles
+// with a single part were finished by k_splat.  Each of the 4 wavefronts sums
+// every 4th part, 4 cells per lane (16-byte loads); the wavefronts are then
+// combined in LDS.
 constexpr int kStripes = kTile / 4;
+constexpr int kRedGroups = kThreads / 64;
 
-__global__ __launch_bounds__(kThreads) void k_splat_reduce(Dev d, int t0, int nt) {
-  const int t = (int)blockIdx.x / kStripes, q = (int)blockIdx.x % kStripes;
-  if (t >= nt) return;
-  const int tile = t0 + t;
-  const int base = d.item_base[tile], np_ = d.item_base[tile + 1] - base;
-  if (np_ <= 1) return;
-  TileGeom T;
-  tile_geom(d, tile, d.tile_patch[tile], T);
-  const PatchDev &P = d.patches[T.p];
-  const StepPatch &W = d.sp[T.p];
-  const int j = 4 * q + ((int)threadIdx.x >> 6), i = threadIdx.x & 63;
-  const float *src = d.partials + (size_t)base * (kTile * kTile) + j * kTile + i;
-  float h0 = 0.f, h1 = 0.f, h2 = 0.f, h3 = 0.f;
-  int s = 0;
-  for (; s + 4 <= np_; s += 4) {
-    h0 += src[(size_t)(s + 0) * (kTile * kTile)];
-    h1 += src[(size_t)(s + 1) * (kTile * kTile)];
-    h2 += src[(size_t)(s + 2) * (kTile * kTile)];
-    h3 += src[(size_t)(s + 3) * (kTile * kTile)];
+__global__ __launch_bounds__(kThreads) void k_splat_reduce(Dev d) {
+  __shared__ float4 red[kRedGroups][64];
+  const int g = (int)threadIdx.x >> 6, l = (int)threadIdx.x & 63;
+  const int nunits = d.splat_ctl[2] * kStripes;
+  constexpr size_t kPart4 = kTile * kTile / 4;   // float4 per partial tile
+  for (int u = (int)blockIdx.x; u < nunits; u += (int)gridDim.x) {
+    const int tile = d.split_tiles[u / kStripes], q = u % kStripes;
+    const int base = d.item_base[tile], np_ = d.item_base[tile + 1] - base;
+    const float4 *src =
+        reinterpret_cast<const float4 *>(d.partials + (size_t)base * (kTile * kTile) + q * 4 * kTile) + l;
+    float4 h0 = make_float4(0.f, 0.f, 0.f, 0.f), h1 = h0;
+    int s = g;
+    for (; s + kRedGroups < np_; s += 2 * kRedGroups) {
+      const float4 a = src[(size_t)s * kPart4], b = src[(size_t)(s + kRedGroups) * kPart4];
+      h0.x += a.x; h0.y += a.y; h0.z += a.z; h0.w += a.w;
+      h1.x += b.x; h1.y += b.y; h1.z += b.z; h1.w += b.w;
+    }
+    if (s < np_) {
+      const float4 a = src[(size_t)s * kPart4];
+      h0.x += a.x; h0.y += a.y; h0.z += a.z; h0.w += a.w;
+    }
+    red[g][l] = make_float4(h0.x + h1.x, h0.y + h1.y, h0.z + h1.z, h0.w + h1.w);
+    __syncthreads();
+    if (g == 0) {
+      float4 h = red[0][l];
+      for (int k = 1; k < kRedGroups; ++k) {
+        const float4 v = red[k][l];
+        h.x += v.x; h.y += v.y; h.z += v.z; h.w += v.w;
+      }
+      TileGeom T;
+      tile_geom(d, tile, d.tile_patch[tile], T);
+      const PatchDev &P = d.patches[T.p];
+      const StepPatch &W = d.sp[T.p];
+      const int c = q * 4 * kTile + 4 * l;   // first of the lane's 4 cells
+      const int j = c / kTile, i = c % kTile;
+      const float hv[4] = {h.x, h.y, h.z, h.w};
+      if (j < T.th)
+        for (int e = 0; e < 4; ++e)
+          if (i + e < T.tw) blend_store(d, P, W, T, i + e, j, hv[e], d.raw, d.blend, 0);
+    }
+    __syncthreads();
   }
-  for (; s < np_; ++s) h0 += src[(size_t)s * (kTile * kTile)];
-  if (i < T.tw && j < T.th) blend_store(d, P, W, T, i, j, (h0 + h1) + (h2 + h3), d.raw, d.blend, 0);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -494,6 +625,12 @@ void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipSt
   const int wpb = kThreads / 64;
   hipLaunchKernelGGL(k_splat_load, dim3((ntiles + wpb - 1) / wpb), dim3(kThreads), 0, st, d, t0, ntiles);
   hipLaunchKernelGGL(k_splat_plan, dim3(1), dim3(kPlanThreads), 0, st, d, t0, ntiles, items_target);
+}
+
+bool bin_plan_fits(int nbins, int ntiles) { return nbins <= kFusedMaxBins && ntiles <= kFusedMaxTiles; }
+
+void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, st, d, nbins, ntiles, items_target);
 }
 
 void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st) {
@@ -508,7 +645,7 @@ void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t 
 
 void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st) {
   if (ntiles <= 0) return;
-  hipLaunchKernelGGL(k_splat_reduce, dim3(kStripes * ntiles), dim3(kThreads), 0, st, d, t0, ntiles);
+  hipLaunchKernelGGL(k_splat_reduce, dim3(std::min(kStripes * ntiles, 8192)), dim3(kThreads), 0, st, d);
 }
 
 void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw, int64_t out_off,

@@ -16,11 +16,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libhwo.so")
 
 HWO_OK, HWO_EINVAL, HWO_ESTATE, HWO_ENOMEM, HWO_EDEVICE, HWO_ERANGE, HWO_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
-STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "splat_plan", "splat_reduce"]
+STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "splat_plan", "splat_reduce",
+          "bin_plan"]
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
-           "hwo_set_timing", "hwo_stage_times", "hwo_record_bytes"]
+           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -90,6 +91,7 @@ def lib():
         "hwo_test_splat": (C.c_int, [vp, i32, P(i64), i64, P(C.c_float), i64]),
         "hwo_set_timing": (C.c_int, [vp, i32]),
         "hwo_stage_times": (C.c_int, [vp, P(C.c_double), P(i64), i32]),
+        "hwo_time_stage": (C.c_int, [vp, i32, i32, P(C.c_double)]),
         "hwo_record_bytes": (i32, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -263,6 +265,12 @@ class Ocean:
         n = np.zeros(len(STAGES), dtype=np.int64)
         self._check(self.L.hwo_stage_times(self.h, _p(ms, C.c_double), _p(n, C.c_int64), len(STAGES)))
         return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def time_stage(self, stage: str, reps: int = 20) -> float:
+        """Mean ms per back-to-back launch of a repeatable stage on the finished frame."""
+        ms = C.c_double(0.0)
+        self._check(self.L.hwo_time_stage(self.h, STAGES.index(stage), int(reps), C.byref(ms)))
+        return float(ms.value)
 
     @property
     def record_bytes(self) -> int:

@@ -83,6 +83,12 @@ def test_call_order_errors(L):
     assert b"set_spectrum" in L.hwo_last_error(h)
     assert L.hwo_step_index(h) == 0
     assert L.hwo_record_bytes(h) == 32
+    ms = C.c_double()
+    # only idempotent stages can be re-launched, and only after a step
+    for stage in (0, 3, 4, 5):   # params, count, scan, scatter
+        assert L.hwo_time_stage(h, stage, 5, C.byref(ms)) == hwo.HWO_EINVAL
+    assert L.hwo_time_stage(h, 6, 5, C.byref(ms)) == hwo.HWO_ESTATE
+    assert L.hwo_time_stage(h, 6, 0, C.byref(ms)) == hwo.HWO_EINVAL
     L.hwo_destroy_ocean(h)
     c2 = cfg(compact=1)
     assert L.hwo_create_ocean(C.byref(c2), C.byref(h)) == hwo.HWO_OK
