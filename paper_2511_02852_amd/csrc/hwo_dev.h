@@ -147,7 +147,7 @@ struct Dev {
   // splat work plan
   uint32_t *tile_load;         // [ntiles] weighted particle count per output tile
   int32_t *item_base;          // [ntiles + 1] first work item of each tile (plan)
-  int32_t *item_tile;          // [max_items] tile of each work item (plan)
+  int4 *item_desc;             // [max_items] tile, part, parts of the tile, patch (plan)
   const int32_t *tile_patch;   // [ntiles] patch of each output tile
   const short4 *tile_rect;     // [ntiles][nb] bins reaching the tile: bx_lo, bx_hi, by_lo, nrows
   int32_t *splat_ctl;          // [1] total items, [2] split tiles (plan)

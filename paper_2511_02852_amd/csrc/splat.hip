@@ -126,7 +126,8 @@ __device__ __forceinline__ void blend_store(const Dev &d, const PatchDev &P, con
 // ---------------------------------------------------------------- load
 // Relative cost of one particle visit (decode plus footprint work) by path:
 // per-lane atomics with 4 or 8 cells per axis, or the matrix-core quadrants.
-constexpr uint32_t kCostSmall4 = 4, kCostSmall8 = 9, kCostMatrix = 40;
+// Ratios fitted to measured item times (about 1 : 2 : 3.5).
+constexpr uint32_t kCostSmall4 = 4, kCostSmall8 = 8, kCostMatrix = 14;
 
 __device__ __forceinline__ uint32_t visit_cost(float rc) {
   const int span = (int)floorf(2.f * rc) + 1;
@@ -231,7 +232,7 @@ __device__ void plan_items(const Dev &d, int t0, int nt, int items_target, const
     if (parts > 1) d.split_tiles[sp++] = t0 + t;
     if (in_lds) s_base[t] = acc;
     else
-      for (int j = 0; j < parts; ++j) d.item_tile[acc + j] = t0 + t;
+      for (int j = 0; j < parts; ++j) d.item_desc[acc + j] = make_int4(t0 + t, j, parts, d.tile_patch[t0 + t]);
     acc += parts;
   }
   if (tid == kPlanThreads - 1) {
@@ -250,7 +251,8 @@ __device__ void plan_items(const Dev &d, int t0, int nt, int items_target, const
       const int mid = (lo + hi + 1) >> 1;
       if (s_base[mid] <= it) lo = mid; else hi = mid - 1;
     }
-    d.item_tile[it] = t0 + lo;
+    const int next = lo + 1 < nt ? s_base[lo + 1] : total;
+    d.item_desc[it] = make_int4(t0 + lo, it - s_base[lo], next - s_base[lo], d.tile_patch[t0 + lo]);
   }
 }
 
@@ -377,21 +379,11 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
 
   for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
     if (tid == 0) {
-      int tile, part, np_;
-      if (direct) {
-        tile = t0 + item;
-        part = 0;
-        np_ = 1;
-      } else {
-        tile = d.item_tile[item];
-        const int base = d.item_base[tile];
-        part = item - base;
-        np_ = d.item_base[tile + 1] - base;
-      }
-      s_tile = tile;
-      s_part = part;
-      s_nparts = np_;
-      s_patch = d.tile_patch[tile];
+      const int4 e = direct ? make_int4(t0 + item, 0, 1, d.tile_patch[t0 + item]) : d.item_desc[item];
+      s_tile = e.x;
+      s_part = e.y;
+      s_nparts = e.z;
+      s_patch = e.w;
     }
     for (int c = tid; c < kTile * kPad; c += kThreads) (&acc[0][0])[c] = 0.f;
     __syncthreads();
