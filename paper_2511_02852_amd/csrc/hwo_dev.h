@@ -21,6 +21,7 @@ constexpr int kNCode = 10368;
 constexpr int kAgeMax = 65535;
 constexpr int kMaxPatches = 127;
 constexpr int kMaxSources = 127;
+constexpr int kMaxInjSlots = 2 * kMaxBuckets * kMaxPatches;   // (patch, bucket, side pair) injection slots
 constexpr int kMaxRing = 128;
 constexpr uint32_t kNoSource = 127;
 constexpr int kTile = 64;          // splat output tile edge (cells)

@@ -34,38 +34,39 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 // Exclusive scan of a[0..len) in place by one block; returns the total.
-__device__ int32_t block_scan_excl(int32_t *a, int len, int32_t *s_tmp /* kThreads + 1 */) {
-  const int tid = threadIdx.x;
+// Each thread scans a run of consecutive entries; the run sums are scanned
+// with wavefront shuffles and one LDS slot per wavefront.
+__device__ int32_t block_scan_excl(int32_t *a, int len, int32_t *s_w /* kThreads / 64 */) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int chunk = (len + kThreads - 1) / kThreads;
-  const int beg = tid * chunk, end = min(len, beg + chunk);
+  const int beg = min(len, tid * chunk), end = min(len, beg + chunk);
   int32_t sum = 0;
   for (int i = beg; i < end; ++i) sum += a[i];
-  s_tmp[tid] = sum;
-  __syncthreads();
-  if (tid == 0) {
-    int32_t acc = 0;
-    for (int i = 0; i < kThreads; ++i) {
-      int32_t v = s_tmp[i];
-      s_tmp[i] = acc;
-      acc += v;
-    }
-    s_tmp[kThreads] = acc;
+  int32_t inc = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
   }
+  if (lane == 63) s_w[wv] = inc;
   __syncthreads();
-  int32_t acc = s_tmp[tid];
+  int32_t acc = inc - sum, total = 0;
+  for (int w = 0; w < kThreads / 64; ++w) {
+    if (w < wv) acc += s_w[w];
+    total += s_w[w];
+  }
   for (int i = beg; i < end; ++i) {
-    int32_t v = a[i];
+    const int32_t v = a[i];
     a[i] = acc;
     acc += v;
   }
   __syncthreads();
-  return s_tmp[kThreads];
+  return total;
 }
 
 // ---------------------------------------------------------------- k_params
 __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
   __shared__ int64_t s_n;
-  __shared__ int32_t s_tmp[kThreads + 1];
+  __shared__ int32_t s_tmp[kThreads / 64];
   const int tid = threadIdx.x;
   if (tid == 0) {
     const int64_t n = d.glob->n + 1;
@@ -231,9 +232,20 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   const int em0 = A.em_lo, nem = B.em_hi - A.em_lo;
   const int total = nex + ninj + nem;
   const int lane = (int)__lane_id();
+  // injection slot offsets and direction CDFs, copied to LDS by the blocks
+  // that hold new boundary particles (their searches then stay in LDS)
+  __shared__ int32_t s_inj[kMaxInjSlots + 1];
+  __shared__ uint32_t s_cdf[kMaxBuckets * kDirBins];
+  bool tables = false;
 
   for (int base = blockIdx.x * kThreads; base < total; base += gridDim.x * kThreads) {
     const int k = base + (int)threadIdx.x;
+    if (!tables && base < nex + ninj && base + kThreads > nex) {   // block-uniform
+      for (int i = threadIdx.x; i <= d.n_inj_slots; i += kThreads) s_inj[i] = d.inj_off[i];
+      for (int i = threadIdx.x; i < d.nb * kDirBins; i += kThreads) s_cdf[i] = d.cdf[i];
+      __syncthreads();
+      tables = true;
+    }
     Part o[3];
     int32_t key[3] = {-1, -1, -1};
     int nout = 0;
@@ -270,9 +282,9 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       int lo = 0, hi = d.n_inj_slots;   // last slot with inj_off[slot] <= gi
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (d.inj_off[mid] <= gi) lo = mid; else hi = mid;
+        if (s_inj[mid] <= gi) lo = mid; else hi = mid;
       }
-      const int slot = lo, j = gi - d.inj_off[slot];
+      const int slot = lo, j = gi - s_inj[slot];
       pid = slot / (2 * d.nb);
       bkt = (slot / 2) % d.nb;
       const int pair = slot & 1;
@@ -280,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       philox4x64(c, d.seed, kStreamInject);
       const uint32_t Q = d.cdfQ[bkt];
       const uint32_t t = (uint32_t)__umul64hi(c[0], (uint64_t)Q);
-      const uint32_t *cdf = d.cdf + bkt * kDirBins;
+      const uint32_t *cdf = s_cdf + bkt * kDirBins;
       int b = 0;   // smallest bin with t < cdf[b]
       for (int step = 32; step > 0; step >>= 1)
         if (cdf[b + step - 1] <= t) b += step;
@@ -330,10 +342,13 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
     if (nout) {
       const PatchDev &P = d.patches[pid];
       const StepPatch W = d.sp[pid];
-      for (int r = 0; r < nout; ++r) {
-        int64_t px, py;
-        key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age, px, py);
-        if (key[r] < 0) ++ndead;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {   // constant bound: o[] and key[] stay in registers
+        if (r < nout) {
+          int64_t px, py;
+          key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age, px, py);
+          if (key[r] < 0) ++ndead;
+        }
       }
     }
     if (!kScatter) {
