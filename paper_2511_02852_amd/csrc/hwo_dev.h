@@ -151,6 +151,9 @@ struct Dev {
   int4 *item_desc;             // [max_items] tile, part, parts of the tile, patch (plan)
   const int32_t *tile_patch;   // [ntiles] patch of each output tile
   const short4 *tile_rect;     // [ntiles][nb] bins reaching the tile: bx_lo, bx_hi, by_lo, nrows
+  uint32_t *tile_meas;         // [ntiles] splat time of the tile this frame (100 MHz ticks)
+  uint32_t *tile_model;        // [ntiles] model estimate the current plan was made from
+  float *tile_ratio;           // [ntiles] running average of measured / estimated (scene mean 1)
   int32_t *splat_ctl;          // [1] total items, [2] split tiles (plan)
   int32_t *split_tiles;        // [ntiles] tiles with more than one part (plan)
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles

@@ -568,9 +568,12 @@ static int finalize(hwo_ocean *o) {
   d.raw = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   // splat work plan
-  d.max_items = d.ntiles + 4096;
+  d.max_items = d.ntiles + 8192;
   d.chunk_load = 2500;   // least estimated cost per work item (a few hundred particle visits)
   d.tile_load = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
+  d.tile_meas = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
+  d.tile_model = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
+  d.tile_ratio = (float *)o->alloc(sizeof(float) * (size_t)std::max(d.ntiles, 1));
   d.item_base = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.ntiles + 1));
   d.splat_ctl = (int32_t *)o->alloc(sizeof(int32_t) * 4);
   d.split_tiles = (int32_t *)o->alloc(sizeof(int32_t) * (size_t)std::max(d.ntiles, 1));
@@ -608,7 +611,8 @@ static int finalize(hwo_ocean *o) {
   }
   if (!d.item_desc) return o->fail(HWO_ENOMEM, "device allocation failed");
   d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
-  if (!d.tile_load || !d.item_base || !d.splat_ctl || !d.split_tiles || !d.partials)
+  if (!d.tile_load || !d.tile_meas || !d.tile_model || !d.tile_ratio || !d.item_base || !d.splat_ctl ||
+      !d.split_tiles || !d.partials)
     return o->fail(HWO_ENOMEM, "device allocation failed");
   if (!d.glob || !d.sp || !d.inj_off || !d.em_off || !d.src_pos || !d.ctr || !d.hist || !d.off || !d.cur ||
       !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
@@ -622,6 +626,9 @@ static int finalize(hwo_ocean *o) {
   HWO_CHECK(hipMemsetAsync(d.blend, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.H, 0, sizeof(float) * (size_t)N * N, o->st));
   HWO_CHECK(hipMemsetAsync(d.tile_load, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.tile_meas, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.tile_model, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
+  HWO_CHECK(hipMemsetD32Async((hipDeviceptr_t)d.tile_ratio, 0x3F800000, (size_t)std::max(d.ntiles, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.item_base, 0, sizeof(int32_t) * ((size_t)d.ntiles + 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.splat_ctl, 0, sizeof(int32_t) * 4, o->st));
   HWO_CHECK(hipStreamSynchronize(o->st));

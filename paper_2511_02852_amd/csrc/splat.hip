@@ -42,9 +42,10 @@ constexpr int kPad = kTile + 1;
 
 // Raised cosine w(t r) for t = d / r: cos^2(pi t / 2) on |t| < 1, else 0.
 // v_cos_f32 takes its argument in revolutions: cos(pi t / 2) = cos(2 pi t / 4).
-__device__ __forceinline__ float wcos(float t) {
-  const float c = __builtin_amdgcn_cosf(0.25f * t);
-  return (fabsf(t) < 1.f) ? c * c : 0.f;
+// Evaluated from q = d / (4 r), the distance in revolutions of the cosine.
+__device__ __forceinline__ float wrev(float q) {
+  const float c = __builtin_amdgcn_cosf(q);
+  return (fabsf(q) < 0.25f) ? c * c : 0.f;
 }
 
 struct TileGeom {
@@ -165,9 +166,14 @@ constexpr int kFusedMaxTiles = 4096;  // tiles of a scene that k_bin_plan handle
 constexpr int kFusedMaxBins = 65536;  // bins of a scene that k_bin_plan handles
 
 // Body of the plan, run by one block of kPlanThreads threads; load[t] is the
-// cost estimate of tile t0 + t (global memory or LDS).
-__device__ void plan_items(const Dev &d, int t0, int nt, int items_target, const uint32_t *load) {
+// model cost estimate of tile t0 + t (global memory or LDS).  It is first
+// corrected by the splat time measured for the tile in the previous frame:
+// each tile keeps a running average of (measured / estimated) relative to the
+// whole scene, and load[t] is scaled by it in place.
+__device__ void plan_items(const Dev &d, int t0, int nt, int items_target, uint32_t *load) {
   __shared__ uint64_t s_red[kPlanThreads / 64];
+  __shared__ uint64_t s_red2[kPlanThreads / 64];
+  __shared__ float s_gm;
   __shared__ int32_t s_cnt[kPlanThreads / 64];
   __shared__ int32_t s_nsp[kPlanThreads / 64];
   __shared__ uint32_t s_chunk;
@@ -176,6 +182,46 @@ __device__ void plan_items(const Dev &d, int t0, int nt, int items_target, const
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int per = (nt + kPlanThreads - 1) / kPlanThreads;
   const int beg = tid * per, end = min(nt, beg + per);
+  // ---- feedback from the previous frame
+  {
+    uint64_t ms = 0, es = 0;
+    for (int t = beg; t < end; ++t) {
+      const uint32_t m = d.tile_meas[t0 + t], e = d.tile_model[t0 + t];
+      if (m && e) {
+        ms += m;
+        es += e;
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      ms += __shfl_xor(ms, o);
+      es += __shfl_xor(es, o);
+    }
+    if (lane == 0) {
+      s_red[wv] = ms;
+      s_red2[wv] = es;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t am = 0, ae = 0;
+      for (int w = 0; w < kPlanThreads / 64; ++w) {
+        am += s_red[w];
+        ae += s_red2[w];
+      }
+      s_gm = (am && ae) ? (float)((double)am / (double)ae) : 0.f;
+    }
+    __syncthreads();
+    const float gm = s_gm;
+    for (int t = beg; t < end; ++t) {
+      const uint32_t m = d.tile_meas[t0 + t], e = d.tile_model[t0 + t];
+      float r = d.tile_ratio[t0 + t];
+      if (gm > 0.f && m && e) r = fminf(4.f, fmaxf(0.25f, 0.5f * r + 0.5f * ((float)m / (float)e) / gm));
+      d.tile_ratio[t0 + t] = r;
+      d.tile_meas[t0 + t] = 0;
+      d.tile_model[t0 + t] = load[t];
+      load[t] = (uint32_t)fminf(4.0e9f, (float)load[t] * r);
+    }
+    __syncthreads();
+  }
   uint64_t mine = 0;
   for (int t = beg; t < end; ++t) mine += load[t];
   uint64_t tot = mine;
@@ -322,7 +368,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // weights in registers, LDS float atomics into the tile.  Loops stop as soon
 // as no lane of the wavefront has work left in them.
 template <int F>
-__device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv, bool valid, float rc, float inv_rc,
+__device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv, bool valid, float rc, float qs,
                                              int tw, int th) {
   int ilo = 0, jlo = 0, nc = 0, nr = 0;
   if (valid && pv.z != 0.f) {
@@ -331,28 +377,31 @@ __device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv
     nc = min(F, min(tw - 1, (int)floorf(pv.x + rc)) - ilo + 1);
     nr = min(F, min(th - 1, (int)floorf(pv.y + rc)) - jlo + 1);
   }
-  float wx[F], wy[F];
+  // offsets of the first column and row from the centre (cells), then
+  // q = offset / (4 r) per cell
+  const float dx0 = (float)ilo - pv.x, dy0 = (float)jlo - pv.y;
+  float wx[F];
 #pragma unroll
   for (int u = 0; u < F; ++u) {
     wx[u] = 0.f;
-    wy[u] = 0.f;
-    if (__any(u < nc)) wx[u] = pv.z * wcos(((float)(ilo + u) - pv.x) * inv_rc);
-    if (__any(u < nr)) wy[u] = wcos(((float)(jlo + u) - pv.y) * inv_rc);
+    if (__any(u < nc)) wx[u] = pv.z * wrev((dx0 + (float)u) * qs);
   }
 #pragma unroll
   for (int jj = 0; jj < F; ++jj) {
     if (!__any(jj < nr)) break;
+    const float wy = wrev((dy0 + (float)jj) * qs);
     float *row = &acc[min(jlo + jj, kTile - 1)][ilo];
 #pragma unroll
     for (int ii = 0; ii < F; ++ii) {
       if (!__any(ii < nc)) break;
-      if (jj < nr && ii < nc) atomicAdd(row + ii, wy[jj] * wx[ii]);
+      if (jj < nr && ii < nc) atomicAdd(row + ii, wy * wx[ii]);
     }
   }
 }
 
 template <class Rec>
-__global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
+// At most 102 registers per lane: five wavefronts per SIMD (five blocks per CU).
+__global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
                                                     int ndirect, float *__restrict__ raw_out,
                                                     float *__restrict__ blend_out, int64_t out_off) {
   __shared__ float acc[kTile][kPad];
@@ -444,6 +493,7 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
     f32x16 cq;
 #pragma unroll
     for (int r = 0; r < 16; ++r) cq[r] = 0.f;
+    const uint64_t t_work = __builtin_amdgcn_s_memrealtime();   // 100 MHz
 
     // The records of chunk c + 1 are loaded while chunk c is splatted.
     Rec rec;
@@ -487,7 +537,7 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
         const int seg_lo = max(c, s_boff[b]) - c, seg_hi = min(c + m, s_boff[b + 1]) - c;
         if (seg_hi <= seg_lo) continue;   // block-uniform
         const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
-        const float inv_rc = 1.f / rc;
+        const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
         const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
         const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
         if (span <= 7) {
@@ -496,15 +546,15 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
             const int q = q0 + lane;
             const bool valid = q < q_hi;
             const float4 pv = pt[valid ? q : q_lo];
-            if (span <= 3) splat_points<4>(acc, pv, valid, rc, inv_rc, T.tw, T.th);
-            else splat_points<8>(acc, pv, valid, rc, inv_rc, T.tw, T.th);
+            if (span <= 3) splat_points<4>(acc, pv, valid, rc, qs, T.tw, T.th);
+            else splat_points<8>(acc, pv, valid, rc, qs, T.tw, T.th);
           }
         } else if (quad_live) {
           // ---- matrix cores: the wavefront's quadrant gets the rank-2 update
           //      D += W_y(:, k1 k2) [A_k1 W_x(k1, :); A_k2 W_x(k2, :)]
           //      for each pair of points that reach it
           const float xlo = (float)xq, ylo = (float)yq;
-          const int mr = lane & 31;
+          const float yrow = (float)(yq + (lane & 31)), xcol = (float)(xq + (lane & 31));
           for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
             const int q = q0 + lane;
             bool hit = false;
@@ -514,20 +564,38 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
                     pv.y - rc < ylo + 31.f;
             }
             uint64_t mask = __ballot(hit);
-            while (mask) {
-              const int k1 = __builtin_ctzll(mask);
+            if (!mask) continue;   // wave-uniform
+            // pairs of hit points; the next pair's point is read from LDS
+            // before the current pair's product is issued
+            auto pop = [&](int &k1, int &k2, float &keep) {
+              k1 = __builtin_ctzll(mask);
               mask &= mask - 1;
-              int k2 = k1;
-              float keep = lane < 32 ? 1.f : 0.f;
+              k2 = k1;
+              keep = lane < 32 ? 1.f : 0.f;
               if (mask) {
                 k2 = __builtin_ctzll(mask);
                 mask &= mask - 1;
                 keep = 1.f;
               }
-              const float4 pv = pt[q0 + (lane < 32 ? k1 : k2)];
-              const float a = wcos(((float)(yq + mr) - pv.y) * inv_rc);
-              const float bw = keep * pv.z * wcos(((float)(xq + mr) - pv.x) * inv_rc);
+            };
+            int k1, k2;
+            float keep;
+            pop(k1, k2, keep);
+            float4 pv = pt[q0 + (lane < 32 ? k1 : k2)];
+            while (true) {
+              const bool more = mask != 0;   // wave-uniform
+              float4 pn = pv;
+              float keep_n = 0.f;
+              if (more) {
+                pop(k1, k2, keep_n);
+                pn = pt[q0 + (lane < 32 ? k1 : k2)];
+              }
+              const float a = wrev((yrow - pv.y) * qs);
+              const float bw = keep * pv.z * wrev((xcol - pv.x) * qs);
               cq = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bw, cq, 0, 0, 0);
+              if (!more) break;
+              pv = pn;
+              keep = keep_n;
             }
           }
         }
@@ -543,6 +611,9 @@ __global__ __launch_bounds__(kThreads) void k_splat(Dev d, int t0, int nt, const
       }
     }
     __syncthreads();
+    // time spent on this item's particles, for the next frame's plan
+    if (tid == 0 && !direct)
+      atomicAdd(&d.tile_meas[tile], (uint32_t)min<uint64_t>(__builtin_amdgcn_s_memrealtime() - t_work, 0x3FFFFFFFull));
 
     if (nparts == 1) {
       const StepPatch &W = d.sp[T.p];
