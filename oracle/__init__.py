@@ -85,6 +85,8 @@ def lib():
         "orc_h0": (C.c_int, [vp, P(dbl), P(dbl)]),
         "orc_set_h0": (C.c_int, [vp, P(dbl), P(dbl)]),
         "orc_splat": (C.c_int, [vp, i32, P(i64), i64, P(dbl)]),
+        "orc_seek": (C.c_int, [vp, i64]),
+        "orc_blend": (C.c_int, [vp, i32, P(dbl), P(dbl), P(dbl)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -296,6 +298,18 @@ class Oracle:
         re = np.ascontiguousarray(z.real, dtype=np.float64)
         im = np.ascontiguousarray(z.imag, dtype=np.float64)
         self._check(self.L.orc_set_h0(self.h, _p(re, C.c_double), _p(im, C.c_double)))
+
+    def seek(self, n: int):
+        """Step index n (with its windows) for evaluating caller-supplied
+        particles and maps; only for an oracle that holds no particles."""
+        self._check(self.L.orc_seek(self.h, int(n)))
+
+    def blend(self, p: int, H: np.ndarray, raw: np.ndarray) -> np.ndarray:
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        raw = np.ascontiguousarray(raw, dtype=np.float64)
+        out = np.zeros_like(raw)
+        self._check(self.L.orc_blend(self.h, p, _p(H, C.c_double), _p(raw, C.c_double), _p(out, C.c_double)))
+        return out
 
     def splat(self, p: int, recs: np.ndarray) -> np.ndarray:
         pt = self.scene.patches[p]

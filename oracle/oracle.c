@@ -1015,6 +1015,29 @@ int orc_patch_maps(orc_ocean *o, int32_t p, const double *H, double *raw, double
     return 0;
 }
 
+/* Set the step index of an oracle that holds no particles, with the windows
+ * of that step, so that caller-supplied particles (orc_splat) and maps
+ * (orc_blend) are evaluated at step n.  The oracle's own state does not
+ * advance: injection, emission and counters are not run. */
+int orc_seek(orc_ocean *o, int64_t n) {
+    if (!o->have_spec) return fail(o, "set_spectrum first");
+    if (o->nP > 0) return fail(o, "seek needs an oracle without particles");
+    if (n < 0) return fail(o, "step must be >= 0");
+    o->stepped = 1;
+    o->n = n;
+    update_windows(o, n);
+    return 0;
+}
+
+/* Blend a caller-supplied raw map of patch p with background H (N x N) at
+ * the current step. */
+int orc_blend(orc_ocean *o, int32_t p, const double *H, const double *raw, double *blended) {
+    if (p < 0 || p >= o->np) return fail(o, "patch out of range");
+    if (!H || !raw || !blended) return fail(o, "null map");
+    blend(o, &o->pt[p], H, raw, blended);
+    return 0;
+}
+
 /* Splat caller-placed particles (canonical records) into a patch map at the
  * current step; used by the closed-form pins. */
 int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *raw) {

@@ -68,6 +68,11 @@ void orc_dft2_inverse(const double *re, const double *im, double *ore, double *o
 int orc_h0(const orc_ocean *o, double *re, double *im);
 int orc_set_h0(orc_ocean *o, const double *re, const double *im);
 int orc_splat(orc_ocean *o, int32_t patch, const int64_t *recs, int64_t n, double *raw);
+/* Step index n (and its windows) for an oracle without particles: evaluation
+ * of caller-supplied particles and maps at that step. */
+int orc_seek(orc_ocean *o, int64_t n);
+/* Blend of a caller-supplied raw patch map with background H at the current step. */
+int orc_blend(orc_ocean *o, int32_t patch, const double *H, const double *raw, double *blended);
 
 #ifdef __cplusplus
 }

@@ -167,6 +167,60 @@ def test_c4_far_anchor():
     say(f"c4 err={e}")
 
 
+@pytest.mark.parametrize("name,frames", [("c3", 900), ("c5", 900)])
+def test_full_size_state(name, frames):
+    """The benchmark's state: frame 900 of the batched scenes in the timed
+    launch configuration (16-byte records, one launch per stage, graph
+    replay).  Identities that hold at any size are checked exactly; heights of
+    sampled patches against the oracle evaluated on the GPU's own particles at
+    that step, and the whole background."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.get(name)
+    npch, nb = len(s.patches), s.spectrum.n_buckets
+    say(f"{name}: {npch} patches, {frames} frames (batched, 16-byte records, graph)")
+    g = hwo.Ocean(s, compact=True, batched=True)
+    done = 0
+    while done < frames:
+        k = min(100, frames - done)
+        g.step(k)
+        done += k
+    g.sync()
+    P = g.particles()
+    say(f"  {P.shape[0]} live particles")
+    live = np.zeros((npch, nb), dtype=np.int64)
+    for p in range(npch):
+        c = g.counts(p)
+        assert np.all(c[:, 5] == 0), f"patch {p}: dropped particles"
+        # every subdivision replaces one particle by three
+        assert np.array_equal(c[:, 0], c[:, 1] + c[:, 2] + 2 * c[:, 3] - c[:, 4]), f"patch {p} conservation"
+        for b in range(nb):
+            assert int(g.tiles(p, b).sum()) == int(c[b, 0]), f"patch {p} bucket {b} histogram"
+        live[p] = c[:, 0]
+    # the particle records: multiplicity per (patch, bucket) and field ranges
+    assert np.array_equal(np.bincount(P[:, 0] * nb + P[:, 1], minlength=npch * nb).reshape(npch, nb), live)
+    kind, level, code, birth, src = P[:, 2], P[:, 3], P[:, 4], P[:, 5], P[:, 8]
+    assert np.all((kind == 0) | (kind == 1))
+    assert np.all((code >= 0) & (code < 10368))
+    assert np.all((birth >= 1) & (birth <= frames))
+    assert np.all(level[kind == 0] == 0) and np.all(src[kind == 0] == -1)
+    assert np.all((level[kind == 1] <= s.spectrum.max_level) & (src[kind == 1] >= 0))
+    # heights
+    o = oracle.Oracle(s)
+    o.seek(frames)
+    H = o.background()
+    e_bg = rel_rms(g.background(), H)
+    assert e_bg <= TOL, f"background rel rms {e_bg}"
+    errs = {}
+    for p in sorted({0, npch // 2, npch - 1}):
+        raw = o.splat(p, P[P[:, 0] == p])
+        e_raw = rel_rms(g.patch_map(p, 1), raw)
+        e_bl = rel_rms(g.patch_map(p, 0), o.blend(p, H, raw))
+        errs[p] = (e_raw, e_bl)
+        assert e_raw <= TOL, f"patch {p} raw rel rms {e_raw}"
+        assert e_bl <= TOL, f"patch {p} blended rel rms {e_bl}"
+    say(f"  bg={e_bg:.2e} patches={errs}")
+
+
 # ---------------------------------------------------------------- splat pins on the GPU
 def pin_scene():
     sp = scenes.Spectrum(U10=10.0, n_buckets=1, lambda_min=1.0, lambda_max=4.0, eta=4.0)

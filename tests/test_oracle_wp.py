@@ -312,3 +312,22 @@ def test_subdivision_conserves_amplitude():
             assert all(x % step == 0 for x in offs)
         checked += 1
     assert checked > 10
+
+
+def test_seek_splat_and_blend_reproduce_patch_maps():
+    """Evaluating a stepped oracle's own particles through seek + splat + blend
+    in a fresh oracle gives the stepped oracle's maps (windows, ages and the
+    blend depend only on the step index)."""
+    s = scenes.c1()
+    a = oracle.Oracle(s)
+    a.step(12)
+    H = a.background()
+    raw, bl = a.patch_maps(0, H)
+    b = oracle.Oracle(s)
+    b.seek(12)
+    assert b.window(0) == a.window(0)
+    raw2 = b.splat(0, a.particles())
+    assert np.allclose(raw2, raw, rtol=0, atol=1e-12 * max(1.0, np.abs(raw).max()))
+    assert np.allclose(b.blend(0, H, raw2), bl, rtol=0, atol=1e-12 * max(1.0, np.abs(bl).max()))
+    with pytest.raises(oracle.OracleError):
+        a.seek(20)   # holds particles
