@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=0)
+    ap.add_argument("--copy-mb", type=int, default=0,
+                    help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build "
@@ -208,6 +210,18 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
                     "avg_launch_ms": round(per_launch[dom], 5),
                     "algorithmic_bytes_per_launch": int(alg[dom])}
+
+    if args.copy_mb > 0:
+        # reference kernel of known traffic for hardware byte counters:
+        # reads and writes exactly copy_mb MiB
+        n = args.copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.copy_mb} MiB done")
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

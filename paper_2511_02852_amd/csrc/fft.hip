@@ -148,14 +148,24 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
   const float dk = (float)(2.0 * M_PI / d.L);
   const float g = (float)d.g;
   float2 *row = buf + f * N;
+  constexpr int E = N / T;   // elements per thread
   if (active) {
     const int mxn = (N - mx) & (N - 1);
     const float kx = dk * (float)signed_idx(mx, N);
     const float2 *__restrict__ ha = d.h0T + (size_t)mx * N;
     const float2 *__restrict__ hb = d.h0T + (size_t)mxn * N;
-    for (int e = t; e < N; e += T) {
-      const int myn = (N - e) & (N - 1);
-      float2 a = ha[e], b = hb[myn];
+    // all loads of the thread first (one round trip), then the evolution
+    float2 av[E], bv[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = t + k * T;
+      av[k] = ha[e];
+      bv[k] = hb[(N - e) & (N - 1)];
+    }
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int e = t + k * T;
+      const float2 a = av[k], b = bv[k];
       float ky = dk * (float)signed_idx(e, N);
       // phase w t in revolutions, reduced to [-1/2, 1/2] for v_sin/v_cos
       const float w = sqrtf(g * sqrtf(fmaf(kx, kx, ky * ky)));
@@ -179,13 +189,17 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
 }
 
 template <int N> struct FftShapeB {
-  static constexpr int F = FftShape<N>::F < N / 2 ? FftShape<N>::F : N / 2;  // row pairs per block
-  static constexpr int T = kThreads / F;
+  // row pairs per block; large transforms take 64 KiB of rows so that each
+  // half-plane row is read in runs of at least 32 bytes
+  static constexpr int F0 = FftShape<N>::F < N / 2 ? FftShape<N>::F : N / 2;
+  static constexpr int F = (N >= 2048) ? 65536 / (8 * N) : F0;
+  static constexpr int B = (N == 2048) ? 2 * kThreads : kThreads;   // threads per block (measured best)
+  static constexpr int T = B / F;
 };
 
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_fft_b(Dev d) {
-  constexpr int F = FftShapeB<N>::F, T = FftShapeB<N>::T;
+__global__ __launch_bounds__(FftShapeB<N>::B) void k_fft_b(Dev d) {
+  constexpr int F = FftShapeB<N>::F, T = FftShapeB<N>::T, B = FftShapeB<N>::B;
   constexpr int C = 2 * F;                    // output rows per block
   __shared__ float2 buf[F * N];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -193,13 +207,27 @@ __global__ __launch_bounds__(kThreads) void k_fft_b(Dev d) {
   // Load the half plane F[0..N/2][jy0 .. jy0+C) with consecutive threads on
   // consecutive column pairs of one row, and rebuild the full x-spectrum:
   // Z[mx] = F_a[mx] + i F_b[mx], Z[N-mx] = conj(F_a[mx]) + i conj(F_b[mx]).
-  for (int q = threadIdx.x; q < (N / 2 + 1) * F; q += kThreads) {
-    const int mx = q / F, f = q % F;
-    const float2 *src = d.FT + (size_t)mx * N + jy0 + 2 * f;
-    const float2 fa = src[0], fb = src[1];
-    float2 *z = buf + f * N;
-    z[mx] = make_float2(fa.x - fb.y, fa.y + fb.x);
-    if (mx > 0 && mx < N / 2) z[N - mx] = make_float2(fa.x + fb.y, fb.x - fa.y);
+  // all loads of the thread first (one round trip), then the repacking
+  constexpr int Q = (N / 2 + 1) * F, K = (Q + B - 1) / B;
+  float4 v[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int q = (int)threadIdx.x + k * B;
+    if (q < Q) {
+      const int mx = q / F, f = q % F;
+      v[k] = *reinterpret_cast<const float4 *>(d.FT + (size_t)mx * N + jy0 + 2 * f);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int q = (int)threadIdx.x + k * B;
+    if (q < Q) {
+      const int mx = q / F, f = q % F;
+      const float2 fa = make_float2(v[k].x, v[k].y), fb = make_float2(v[k].z, v[k].w);
+      float2 *z = buf + f * N;
+      z[mx] = make_float2(fa.x - fb.y, fa.y + fb.x);
+      if (mx > 0 && mx < N / 2) z[N - mx] = make_float2(fa.x + fb.y, fb.x - fa.y);
+    }
   }
   __syncthreads();
   const int f = threadIdx.x / T, t = threadIdx.x % T;
@@ -288,7 +316,7 @@ template <int N> static void fft_a_n(const Dev &d, hipStream_t st) {
 }
 template <int N> static void fft_b_n(const Dev &d, hipStream_t st) {
   constexpr int F = FftShapeB<N>::F;
-  hipLaunchKernelGGL(k_fft_b<N>, dim3(N / (2 * F)), dim3(kThreads), 0, st, d);
+  hipLaunchKernelGGL(k_fft_b<N>, dim3(N / (2 * F)), dim3(FftShapeB<N>::B), 0, st, d);
 }
 
 void launch_fft_a(const Dev &d, hipStream_t st) {

@@ -237,9 +237,19 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   __shared__ int32_t s_inj[kMaxInjSlots + 1];
   __shared__ uint32_t s_cdf[kMaxBuckets * kDirBins];
   bool tables = false;
+  // the record of the thread's next previous particle is loaded one
+  // iteration ahead
+  const int stride = (int)gridDim.x * kThreads;
+  Rec rec_next;
+  {
+    const int k0 = (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    if (k0 < nex) rec_next = Sin[ex0 + k0];
+  }
 
-  for (int base = blockIdx.x * kThreads; base < total; base += gridDim.x * kThreads) {
+  for (int base = blockIdx.x * kThreads; base < total; base += stride) {
     const int k = base + (int)threadIdx.x;
+    const Rec rec = rec_next;
+    if (k + stride < nex) rec_next = Sin[ex0 + k + stride];
     if (!tables && base < nex + ninj && base + kThreads > nex) {   // block-uniform
       for (int i = threadIdx.x; i <= d.n_inj_slots; i += kThreads) s_inj[i] = d.inj_off[i];
       for (int i = threadIdx.x; i < d.nb * kDirBins; i += kThreads) s_cdf[i] = d.cdf[i];
@@ -254,7 +264,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
     uint32_t ndead = 0;
     if (k < nex) {
       // ---- a previous particle: subdivide, then survive
-      Part q = RecIO<Rec>::load(Sin, ex0 + k, n);
+      Part q = RecIO<Rec>::unpack(rec, n);
       if (!RecIO<Rec>::kHasAmp && q.age == 0) q.age = 65536;   // 16-bit birth wrapped: expired
       pid = (int)m_patch(q.meta);
       bkt = (int)m_bucket(q.meta);

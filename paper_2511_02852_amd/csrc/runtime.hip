@@ -635,7 +635,7 @@ static int finalize(hwo_ocean *o) {
   int dev_id = 0, cus = 256;
   (void)hipGetDevice(&dev_id);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
-  o->update_grid = std::max(64, 4 * cus);
+  o->update_grid = std::max(64, 6 * cus);   // six blocks per CU are resident (75 registers per lane)
   o->target_blocks = std::max(64, 4 * cus);
   if (o->cfg.batched) {
     o->fused = bin_plan_fits(d.nbins, d.ntiles);
