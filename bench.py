@@ -100,6 +100,26 @@ def splat_flops(ocean, scene):
     return flops
 
 
+DOM_KERNEL = {"splat": "k_splat<RecCompact>", "fft_a": "k_fft_a", "fft_b": "k_fft_b",
+              "count": "k_update<RecCompact, false>", "scatter": "k_update<RecCompact, true>"}
+
+
+def measured_traffic(config, dom):
+    """HBM bytes per launch of the dominant kernel from profiles/traffic.json
+    (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a device copy of known size), or None when there is no entry
+    for this workload and kernel or the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    e = json.load(open(path)).get(config)
+    if not e or e.get("kernel") != DOM_KERNEL.get(dom):
+        return None
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in e["sources"])).hexdigest()
+    return int(e["bytes_per_launch"]) if h == e["sources_sha256"] else None
+
+
 def cpu_baseline(scene, preroll, nframes):
     """Time the FP64 oracle (one thread) on nframes full frames after the pre-roll."""
     import oracle
@@ -197,17 +217,18 @@ def main():
     t = per_launch[dom] * 1e-3
     t_hbm = alg[dom] / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops / (FP32_PEAK_TFLOPS * 1e12) if dom == "splat" else 0.0
+    traffic = measured_traffic(args.config, dom)
     if t_mfma > t_hbm:
         achieved = flops / t / 1e12 if t > 0 else 0.0
         roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": traffic,
                     "avg_launch_ms": round(per_launch[dom], 5), "algorithmic_flops_per_launch": int(flops),
                     "algorithmic_bytes_per_launch": int(alg[dom]),
                     "hbm_frac": round(t_hbm / t, 5) if t > 0 else None}
     else:
         achieved = alg[dom] / t / 1e9 if t > 0 else 0.0
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                     "avg_launch_ms": round(per_launch[dom], 5),
                     "algorithmic_bytes_per_launch": int(alg[dom])}
 
