@@ -12,9 +12,12 @@
 //
 // Work decomposition.  The output of every patch is cut into 64x64 tiles.
 // k_splat_load estimates each tile's cost from the particles its items will
-// visit (bin offsets of this step, weighted by path); k_splat_plan turns the
-// loads into a number of parts per tile (about equal cost per part, within a
-// total item budget) and a prefix of work items.  k_splat is a grid over the
+// visit (bin offsets of this step, weighted by path); k_splat_plan corrects
+// the estimates by the time each tile took in the previous frame and turns
+// them into a number of parts per tile (about equal cost per part, within a
+// total item budget) and a prefix of work items (k_bin_plan does the scan,
+// the estimates and the plan in one block for small scenes).  k_splat is a
+// grid over the
 // items: an item is one part of one tile, i.e. one of `nparts` equal shares
 // of each bucket's list of particles that can reach the tile.  That list is
 // the bins whose crests lie within 2 r_b of the tile, contiguous runs of the
