@@ -651,18 +651,21 @@ __global__ __launch_bounds__(kThreads) void k_splat_reduce(Dev d) {
     const int base = d.item_base[tile], np_ = d.item_base[tile + 1] - base;
     const float4 *src =
         reinterpret_cast<const float4 *>(d.partials + (size_t)base * (kTile * kTile) + q * 4 * kTile) + l;
-    float4 h0 = make_float4(0.f, 0.f, 0.f, 0.f), h1 = h0;
-    int s = g;
-    for (; s + kRedGroups < np_; s += 2 * kRedGroups) {
-      const float4 a = src[(size_t)s * kPart4], b = src[(size_t)(s + kRedGroups) * kPart4];
-      h0.x += a.x; h0.y += a.y; h0.z += a.z; h0.w += a.w;
-      h1.x += b.x; h1.y += b.y; h1.z += b.z; h1.w += b.w;
+    // the wavefront sums parts g, g + 4, ...; eight loads in flight per lane
+    float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int s0 = g; s0 < np_; s0 += 8 * kRedGroups) {
+      float4 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int s = s0 + k * kRedGroups;
+        v[k] = s < np_ ? src[(size_t)s * kPart4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        h.x += v[k].x; h.y += v[k].y; h.z += v[k].z; h.w += v[k].w;
+      }
     }
-    if (s < np_) {
-      const float4 a = src[(size_t)s * kPart4];
-      h0.x += a.x; h0.y += a.y; h0.z += a.z; h0.w += a.w;
-    }
-    red[g][l] = make_float4(h0.x + h1.x, h0.y + h1.y, h0.z + h1.z, h0.w + h1.w);
+    red[g][l] = h;
     __syncthreads();
     if (g == 0) {
       float4 h = red[0][l];
