@@ -146,7 +146,7 @@ struct Dev {
   float *H;                    // [N][N]
   float *raw, *blend;          // heights, all patches
   // splat work plan
-  uint32_t *tile_load;         // [ntiles] weighted particle count per output tile
+  uint32_t *tile_load;         // [ntiles] estimated splat cost per output tile (model units)
   int32_t *item_base;          // [ntiles + 1] first work item of each tile (plan)
   int4 *item_desc;             // [max_items] tile, part, parts of the tile, patch (plan)
   const int32_t *tile_patch;   // [ntiles] patch of each output tile
@@ -158,7 +158,7 @@ struct Dev {
   int32_t *split_tiles;        // [ntiles] tiles with more than one part (plan)
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
   int32_t max_items;           // capacity of partials (items)
-  uint32_t chunk_load;         // target load per work item
+  uint32_t chunk_load;         // least estimated cost of a work item
 };
 
 // ---------------------------------------------------------------- helpers

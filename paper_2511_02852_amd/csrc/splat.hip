@@ -530,8 +530,18 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
         Tb.Ab = P.A[b];
         if (!load_item<Rec>(d, rec, n, b, Tb, cx, cy, A, u)) A = 0.f;
         const float rc = d.bucket_r[b] / (float)P.dx;
-        pt[2 * tid] = make_float4(cx, cy, A, 0.f);
-        pt[2 * tid + 1] = make_float4(cx - rc * u.x, cy - rc * u.y, -A, 0.f);
+        const float tx = cx - rc * u.x, ty = cy - rc * u.y;
+        // quadrants of the tile a footprint reaches (bit w: quadrant of
+        // wavefront w), used by the matrix-core path
+        auto quads = [&](float x, float y) {
+          if (A == 0.f) return 0u;
+          const bool x0 = x - rc < 31.f && x + rc > 0.f, x1 = x - rc < 63.f && x + rc > 32.f;
+          const bool y0 = y - rc < 31.f && y + rc > 0.f, y1 = y - rc < 63.f && y + rc > 32.f;
+          return (uint32_t)(x0 && y0) | (uint32_t)(x1 && y0) << 1 | (uint32_t)(x0 && y1) << 2 |
+                 (uint32_t)(x1 && y1) << 3;
+        };
+        pt[2 * tid] = make_float4(cx, cy, A, __uint_as_float(quads(cx, cy)));
+        pt[2 * tid + 1] = make_float4(tx, ty, -A, __uint_as_float(quads(tx, ty)));
       }
       __syncthreads();
       if (c + kChunk < Mi) fetch(c + kChunk);
@@ -556,16 +566,10 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
           // ---- matrix cores: the wavefront's quadrant gets the rank-2 update
           //      D += W_y(:, k1 k2) [A_k1 W_x(k1, :); A_k2 W_x(k2, :)]
           //      for each pair of points that reach it
-          const float xlo = (float)xq, ylo = (float)yq;
           const float yrow = (float)(yq + (lane & 31)), xcol = (float)(xq + (lane & 31));
           for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
             const int q = q0 + lane;
-            bool hit = false;
-            if (q < q_hi) {
-              const float4 pv = pt[q];
-              hit = pv.z != 0.f && pv.x + rc > xlo && pv.x - rc < xlo + 31.f && pv.y + rc > ylo &&
-                    pv.y - rc < ylo + 31.f;
-            }
+            const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
             uint64_t mask = __ballot(hit);
             if (!mask) continue;   // wave-uniform
             // pairs of hit points; the next pair's point is read from LDS
