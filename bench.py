@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -35,7 +36,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ms/frame & particle splats/s (batched FP16-attr vs plain FP32); FFT GB/s"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
-PREROLL = {"c1": 0, "c2": 540, "c3": 900, "c4": 540, "c5": 900}
+PREROLL = {"c1": 0, "c2": 540, "c3": 900, "c4": 540, "c5": 900, "p0": 3540}
 
 
 def log(*a):
@@ -86,16 +87,14 @@ def algorithmic(scene, rec_bytes, n_live):
 def splat_flops(ocean, scene):
     """FP32 flops of the splat as a contraction: every crest and trough adds
     A w(d_x) w(d_y) to the cells of its (2 r / dx)^2 square footprint (on
-    average), one multiply-add per cell.  r_b is half the bucket's
-    geometric-mean wavelength (deep-water r = pi g / w^2)."""
-    sp = scene.spectrum
-    lam = [sp.lambda_min * (sp.lambda_max / sp.lambda_min) ** ((i + 0.5) / sp.n_buckets)
-           for i in range(sp.n_buckets)]
+    average), one multiply-add per cell.  Radii come from the library's
+    bucket table."""
+    r = ocean.buckets()[:, 2]
     flops = 0.0
     for p, P in enumerate(scene.patches):
         live = ocean.counts(p, allow_overflow=True)[:, 0]
-        for i in range(sp.n_buckets):
-            rc = 0.5 * lam[i] / P.dx
+        for i in range(len(r)):
+            rc = r[i] / P.dx
             flops += float(live[i]) * 2.0 * (2.0 * rc) ** 2 * 2.0
     return flops
 
@@ -135,6 +134,55 @@ def cpu_baseline(scene, preroll, nframes):
     return dt * 1e3 / nframes, dt
 
 
+def bins_for(ocean, scene):
+    """Bin edge (cells) per bucket from the library's bucket radii: at least 8
+    cells, doubled while below the wavelength (up to 32 cells), and further
+    while a 64-cell tile would need more than 32 bin rows."""
+    r = ocean.buckets()[:, 2]
+    dx = min(p.dx for p in scene.patches)
+    out = []
+    for ri in r:
+        cells = 2.0 * ri / dx
+        b = 8
+        while (b < cells and b < 32) or (64 + 8.0 * ri / dx) / b + 1 > 32:
+            b *= 2
+        out.append(b)
+    return out
+
+
+def trends(K, W):
+    """The paper's default scene (U10 = 5, N_omega = N_theta = 16) over wind
+    speed and sampling density, each run to the steady state of its slowest
+    waves: the cost trends of the paper's parameter table."""
+    import dataclasses
+    import torch
+    from paper_2511_02852_amd import hwo, scenes
+    base = scenes.p0()
+    runs = [(u, 16) for u in (3.0, 5.0, 10.0, 15.0)] + [(5.0, 8), (5.0, 12)]
+    rows = []
+    for u10, ns in runs:
+        sp = dataclasses.replace(base.spectrum, U10=u10, n_buckets=ns, eta=float(ns))
+        sc = base.replace(spectrum=sp, bins=[32] * ns)
+        probe = hwo.Ocean(sc, compact=True, batched=True)
+        bins = bins_for(probe, sc)
+        c_min = float(probe.buckets()[:, 3].min())
+        probe.close()
+        sc = sc.replace(bins=bins)
+        size = max(p.nx * p.dx for p in sc.patches)
+        pre = int(math.ceil(size / (c_min * sc.dt))) + 60
+        g = hwo.Ocean(sc, compact=True, batched=True)
+        spin(g, pre)
+        spin(g, W)
+        ms = time_frames(g, K)
+        live = live_total(g, sc)
+        g.close()
+        rows.append({"U10": u10, "n_omega": ns, "n_theta": ns, "ms_per_frame": round(ms, 5),
+                     "live_particles": live, "preroll_frames": pre})
+        log(f"[trends] U10={u10} N={ns}: {ms:.4f} ms/frame, {live} live particles")
+    torch.cuda.synchronize()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +192,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=0)
+    ap.add_argument("--trends", action="store_true",
+                    help="paper-default scene over wind speeds and sampling densities (Table 2 trends)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -159,6 +209,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.trends:
+        rows = trends(args.steps, args.warmup)
+        print(json.dumps({"metric": "ms/frame of the paper-default scene over U10 and (N_omega, N_theta)",
+                          "unit": "ms/frame", "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "data": "synthetic", "trends": rows}), flush=True)
+        return
     scene = scenes.get(args.config)
     preroll = PREROLL.get(args.config, 0)
     K, W = args.steps, args.warmup

@@ -82,6 +82,9 @@ typedef struct {
     int32_t max_level;      /* subdivision levels of ring particles, 0..4 */
     double subdiv_frac;     /* split when ring spacing > subdiv_frac * radius */
     int32_t h0_mode;        /* 0 Gaussian h0, 1 unit modulus */
+    int32_t bucket_mode;    /* 0: n_buckets log-spaced wavelength buckets over
+                               [lambda_min, lambda_max]; 1: equal-energy buckets
+                               over [0.5 w_p, 2.5 w_p] (Sec 3.3), lambda range unused */
 } hwo_spectrum;
 
 typedef struct {
@@ -134,6 +137,11 @@ int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst,
  * Returns HWO_EOVERFLOW (with valid counts) if particles were dropped. */
 int hwo_read_counts(hwo_ocean *o, int32_t patch, int64_t *dst, int64_t dst_elems);
 
+/* Frequency buckets after set_spectrum (Sec 3.2-3.3): four doubles per bucket,
+ * w_i (rad/s), dw_i (rad/s), particle radius r_i = pi g / w_i^2 (m) and phase
+ * speed c_i = g / w_i (m/s); bucket 0 holds the shortest waves.  n >= 4
+ * n_buckets, else HWO_ERANGE; HWO_ESTATE before set_spectrum. */
+int hwo_read_buckets(const hwo_ocean *o, double *dst, int32_t n);
 /* Bin grid of (patch, bucket): dims = {bin edge cells, nbx, nby}. */
 int hwo_tile_dims(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dims);
 /* Live particles per bin, row-major [by][bx], bins anchored at the window

@@ -231,13 +231,40 @@ const char *orc_error(const orc_ocean *o) { return o ? o->err : "null ocean"; }
 
 static void gen_h0(orc_ocean *o);
 
+/* Equal-energy partition of the sampling band [0.5 w_p, 2.5 w_p] into n
+ * buckets (Sec 3.3): ascending edges e[0..n] with equal integrals of S_J
+ * between neighbours.  The cumulative integral is composite Simpson over
+ * 65536 panels; an edge is placed by linear interpolation of the cumulative
+ * integral inside the panel that contains its target. */
+static void equal_energy_edges(const orc_ocean *o, int n, double *e) {
+    const int K = 65536;
+    const double a = 0.5 * o->wp, b = 2.5 * o->wp, h = (b - a) / (double)K;
+    double *C = (double *)malloc(sizeof(double) * (size_t)(K + 1));
+    C[0] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        const double x = a + (double)k * h;
+        C[k + 1] = C[k] + h / 6.0 * (orc_jonswap(o, x) + 4.0 * orc_jonswap(o, x + 0.5 * h) + orc_jonswap(o, x + h));
+    }
+    e[0] = a;
+    e[n] = b;
+    int k = 0;
+    for (int i = 1; i < n; ++i) {
+        const double tau = C[K] * (double)i / (double)n;
+        while (k < K - 1 && C[k + 1] <= tau) ++k;
+        e[i] = a + (double)k * h + h * ((tau - C[k]) / (C[k + 1] - C[k]));
+    }
+    free(C);
+}
+
 int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, double spread_s,
                      double wind_dir, int32_t n_buckets, double lambda_min, double lambda_max,
-                     double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode) {
+                     double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode,
+                     int32_t bucket_mode) {
     if (o->have_spec) return fail(o, "spectrum already set");
     if (!(U10 > 0) || !(fetch > 0)) return fail(o, "U10 and fetch must be positive");
     if (n_buckets < 1 || n_buckets > MAXB) return fail(o, "n_buckets out of range");
-    if (!(lambda_min > 0) || !(lambda_max > lambda_min)) return fail(o, "bad lambda range");
+    if (bucket_mode != 0 && bucket_mode != 1) return fail(o, "bucket_mode must be 0 or 1");
+    if (bucket_mode == 0 && (!(lambda_min > 0) || !(lambda_max > lambda_min))) return fail(o, "bad lambda range");
     if (!(eta > 0)) return fail(o, "eta must be positive");
     if (max_level < 0 || max_level > LMAX_CAP) return fail(o, "max_level out of range");
     if (!(subdiv_frac > 0)) return fail(o, "subdiv_frac must be positive");
@@ -258,12 +285,20 @@ int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, doubl
     o->wp = 22.0 * pow(g * g / (U10 * fetch), 1.0 / 3.0);
     o->gamma = (gamma > 0.0) ? gamma : 7.0 * pow(g * fetch / (U10 * U10), -0.142);
 
-    /* Buckets: log-spaced wavelength edges, w_i the geometric mean of the
-     * edge frequencies, dw_i the edge difference; Sec 3.2 kinematics. */
+    /* Buckets: edge frequencies in descending order (bucket 0 holds the
+     * shortest waves), either from log-spaced wavelength edges or from the
+     * equal-energy partition of [0.5 w_p, 2.5 w_p]; w_i the geometric mean of
+     * the edge frequencies, dw_i the edge difference; Sec 3.2 kinematics. */
     double we[MAXB + 1];
-    for (int j = 0; j <= n_buckets; ++j) {
-        double le = lambda_min * pow(lambda_max / lambda_min, (double)j / (double)n_buckets);
-        we[j] = sqrt(2.0 * M_PI * g / le);
+    if (bucket_mode == 0) {
+        for (int j = 0; j <= n_buckets; ++j) {
+            double le = lambda_min * pow(lambda_max / lambda_min, (double)j / (double)n_buckets);
+            we[j] = sqrt(2.0 * M_PI * g / le);
+        }
+    } else {
+        double e[MAXB + 1];
+        equal_energy_edges(o, n_buckets, e);
+        for (int j = 0; j <= n_buckets; ++j) we[j] = e[n_buckets - j];
     }
     for (int i = 0; i < n_buckets; ++i) {
         double w = sqrt(we[i] * we[i + 1]);

@@ -4,7 +4,8 @@
 //
 // Setup tables (built once, in FP64, on the host; integer ones are exact):
 //   spectrum   Eq 2-4 (alpha, w_p, gamma), Eq 5-6 spreading
-//   buckets    log-spaced wavelength edges, w_i = geometric mean of the edge
+//   buckets    log-spaced wavelength edges or the equal-energy partition of
+//              [0.5 w_p, 2.5 w_p], w_i = geometric mean of the edge
 //              frequencies, r_i = pi g / w_i^2, c_i = g / w_i (Sec 3.2)
 //   directions 64 bins, integer weights round(Dir dtheta 2^30), codes in units
 //              of 2 pi / 10368; CDF by a wave64 scan on the GPU
@@ -149,6 +150,30 @@ static double jonswap_h(const hwo_ocean *o, double w) {
   return o->alpha * o->cfg.g * o->cfg.g * pow(w, -5.0) * exp(-1.25 * x4) * pow(o->gamma, r);
 }
 
+// Equal-energy partition of [0.5 w_p, 2.5 w_p] into n buckets (Sec 3.3):
+// ascending edges with equal integrals of S_J between neighbours.  The
+// cumulative integral is composite Simpson over 65536 panels; an edge is
+// placed by linear interpolation of the cumulative integral inside the panel
+// that contains its target.
+static void equal_energy_edges(const hwo_ocean *o, int n, double *e) {
+  const int K = 65536;
+  const double a = 0.5 * o->wp, b = 2.5 * o->wp, h = (b - a) / (double)K;
+  std::vector<double> C((size_t)K + 1);
+  C[0] = 0.0;
+  for (int k = 0; k < K; ++k) {
+    const double x = a + (double)k * h;
+    C[k + 1] = C[k] + h / 6.0 * (jonswap_h(o, x) + 4.0 * jonswap_h(o, x + 0.5 * h) + jonswap_h(o, x + h));
+  }
+  e[0] = a;
+  e[n] = b;
+  int k = 0;
+  for (int i = 1; i < n; ++i) {
+    const double tau = C[K] * (double)i / (double)n;
+    while (k < K - 1 && C[k + 1] <= tau) ++k;
+    e[i] = a + (double)k * h + h * ((tau - C[k]) / (C[k + 1] - C[k]));
+  }
+}
+
 static double spread_h(const hwo_ocean *o, double w) {
   if (o->sp.spread_s >= 0.0) return o->sp.spread_s;
   double mu = (w <= o->wp) ? 5.0 : -2.5;
@@ -202,7 +227,9 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   if (o->have_spec) return o->fail(HWO_ESTATE, "spectrum already set");
   if (!(sp->U10 > 0) || !(sp->fetch > 0)) return o->fail(HWO_EINVAL, "U10 and fetch must be positive");
   if (sp->n_buckets < 1 || sp->n_buckets > kMaxBuckets) return o->fail(HWO_EINVAL, "n_buckets out of range");
-  if (!(sp->lambda_min > 0) || !(sp->lambda_max > sp->lambda_min)) return o->fail(HWO_EINVAL, "bad lambda range");
+  if (sp->bucket_mode != 0 && sp->bucket_mode != 1) return o->fail(HWO_EINVAL, "bucket_mode must be 0 or 1");
+  if (sp->bucket_mode == 0 && (!(sp->lambda_min > 0) || !(sp->lambda_max > sp->lambda_min)))
+    return o->fail(HWO_EINVAL, "bad lambda range");
   if (!(sp->eta > 0)) return o->fail(HWO_EINVAL, "eta must be positive");
   if (sp->max_level < 0 || sp->max_level > kMaxLevel) return o->fail(HWO_EINVAL, "max_level out of range");
   if (!(sp->subdiv_frac > 0)) return o->fail(HWO_EINVAL, "subdiv_frac must be positive");
@@ -216,11 +243,17 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   o->alpha = 0.076 * pow(U10 * U10 / (fetch * g), 0.22);
   o->wp = 22.0 * pow(g * g / (U10 * fetch), 1.0 / 3.0);
   o->gamma = (sp->gamma > 0.0) ? sp->gamma : 7.0 * pow(g * fetch / (U10 * U10), -0.142);
-  // buckets
+  // buckets: edge frequencies descending (bucket 0 holds the shortest waves)
   double we[kMaxBuckets + 1];
-  for (int j = 0; j <= o->nb; ++j) {
-    double le = sp->lambda_min * pow(sp->lambda_max / sp->lambda_min, (double)j / (double)o->nb);
-    we[j] = sqrt(2.0 * M_PI * g / le);
+  if (sp->bucket_mode == 0) {
+    for (int j = 0; j <= o->nb; ++j) {
+      double le = sp->lambda_min * pow(sp->lambda_max / sp->lambda_min, (double)j / (double)o->nb);
+      we[j] = sqrt(2.0 * M_PI * g / le);
+    }
+  } else {
+    double e[kMaxBuckets + 1];
+    equal_energy_edges(o, o->nb, e);
+    for (int j = 0; j <= o->nb; ++j) we[j] = e[o->nb - j];
   }
   for (int i = 0; i < o->nb; ++i) {
     double w = sqrt(we[i] * we[i + 1]);
@@ -868,6 +901,19 @@ int hwo_read_counts(hwo_ocean *o, int32_t patch, int64_t *dst, int64_t dst_elems
   }
   if (g.err) return o->fail(HWO_ERANGE, "a window left the fixed-point position range");
   if (g.dropped) return o->fail(HWO_EOVERFLOW, "particle capacity exceeded");
+  return HWO_OK;
+}
+
+int hwo_read_buckets(const hwo_ocean *o, double *dst, int32_t n) {
+  if (!o || !dst) return HWO_EINVAL;
+  if (!o->have_spec) return HWO_ESTATE;
+  if (n < 4 * o->nb) return HWO_ERANGE;
+  for (int i = 0; i < o->nb; ++i) {
+    dst[4 * i + 0] = o->w[i];
+    dst[4 * i + 1] = o->dw[i];
+    dst[4 * i + 2] = o->r[i];
+    dst[4 * i + 3] = o->c[i];
+  }
   return HWO_OK;
 }
 

@@ -20,7 +20,7 @@ STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "spla
           "bin_plan"]
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
-           "hwo_read_counts", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
+           "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
            "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -38,7 +38,8 @@ class HwoSpectrum(C.Structure):
     _fields_ = [("U10", C.c_double), ("fetch", C.c_double), ("gamma", C.c_double), ("spread_s", C.c_double),
                 ("wind_dir", C.c_double), ("n_buckets", C.c_int32), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("eta", C.c_double), ("max_level", C.c_int32),
-                ("subdiv_frac", C.c_double), ("h0_mode", C.c_int32)]
+                ("subdiv_frac", C.c_double), ("h0_mode", C.c_int32),
+                ("bucket_mode", C.c_int32)]
 
 
 class HwoPatch(C.Structure):
@@ -85,6 +86,7 @@ def lib():
         "hwo_step_index": (i64, [vp]),
         "hwo_read_heightmaps": (C.c_int, [vp, i32, i32, vp, i64, i32]),
         "hwo_read_counts": (C.c_int, [vp, i32, P(i64), i64]),
+        "hwo_read_buckets": (C.c_int, [vp, P(C.c_double), i32]),
         "hwo_tile_dims": (C.c_int, [vp, i32, i32, P(i64)]),
         "hwo_read_tiles": (C.c_int, [vp, i32, i32, P(i64), i64]),
         "hwo_read_particles": (C.c_int, [vp, P(i64), i64, P(i64)]),
@@ -162,7 +164,8 @@ class Ocean:
         self._check(self.L.hwo_create_ocean(C.byref(cfg), C.byref(self.h)))
         sp = scene.spectrum
         hs = HwoSpectrum(sp.U10, sp.fetch, sp.gamma, sp.spread_s, sp.wind_dir, sp.n_buckets, sp.lambda_min,
-                         sp.lambda_max, sp.eta, sp.max_level, sp.subdiv_frac, sp.h0_mode)
+                         sp.lambda_max, sp.eta, sp.max_level, sp.subdiv_frac, sp.h0_mode,
+                         sp.bucket_mode)
         self._check(self.L.hwo_set_spectrum(self.h, C.byref(hs)))
         self.nb = sp.n_buckets
         pid = C.c_int32()
@@ -233,6 +236,12 @@ class Ocean:
         d = np.zeros(3, dtype=np.int64)
         self._check(self.L.hwo_tile_dims(self.h, p, b, _p(d, C.c_int64)))
         return int(d[0]), int(d[1]), int(d[2])
+
+    def buckets(self) -> np.ndarray:
+        """Per bucket: w_i, dw_i, radius r_i (m), phase speed c_i (m/s)."""
+        out = np.zeros((self.nb, 4))
+        self._check(self.L.hwo_read_buckets(self.h, _p(out, C.c_double), out.size))
+        return out
 
     def tiles(self, p: int, b: int) -> np.ndarray:
         _, nbx, nby = self.tile_dims(p, b)

@@ -39,6 +39,8 @@ class Spectrum:
     max_level: maximum subdivision level of source particles (<= 4).
     subdiv_frac: split when neighbour spacing exceeds subdiv_frac * radius.
     h0_mode: 0 Gaussian h0 amplitudes, 1 unit-modulus (deterministic variance).
+    bucket_mode: 0 log-spaced wavelength buckets over [lambda_min, lambda_max];
+      1 equal-energy buckets over [0.5 w_p, 2.5 w_p] (the lambda range is unused).
     """
     U10: float = 10.0
     fetch: float = 100e3
@@ -52,6 +54,7 @@ class Spectrum:
     max_level: int = 4
     subdiv_frac: float = 0.5
     h0_mode: int = 0
+    bucket_mode: int = 0
 
 
 @dataclass
@@ -229,7 +232,26 @@ def c5() -> Scene:
                  bins=default_bins(16, 0.25, 64.0, 0.25), compact=True, batched=True)
 
 
-SCENES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+def p0() -> Scene:
+    """The paper's default parameters (Sec 5): U10 = 5 m/s, fetch 10 km,
+    N_omega = N_theta = 16, a 100 m wave-particle region at 512^2 cells and a
+    500 m FFT ocean at 512^2.  Buckets are the paper's equal-energy partition
+    of [0.5 w_p, 2.5 w_p], spreading is Mitsuyasu's s(w) and gamma follows
+    from the fetch.  The region follows a small moving source (a boat).
+    About 0.9M particles are live after the ~3600 steps that the slowest
+    waves need to cross the region.  Bin edges (cells) are chosen for this
+    spectrum's bucket wavelengths (about 1.8-19.7 m, i.e. 9-101 cells)."""
+    sp = Spectrum(U10=5.0, fetch=10e3, gamma=0.0, spread_s=-1.0, wind_dir=0.0,
+                  n_buckets=16, lambda_min=1.0, lambda_max=2.0, eta=16.0, bucket_mode=1)
+    h = math.radians(30.0)
+    src = Source(x0=250.0, y0=250.0, vx=3.0 * math.cos(h), vy=3.0 * math.sin(h),
+                 radius=2.5, draft=0.5, ring_n=64, patch=0)
+    p = Patch(anchor_x=250.0, anchor_y=250.0, nx=512, ny=512, dx=100.0 / 512, follow=0)
+    return Scene(name="p0-paper-default", fft_n=512, fft_L=500.0, seed=0, steps=3600,
+                 spectrum=sp, patches=[p], sources=[src], bins=[16, 16] + [32] * 14)
+
+
+SCENES = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "p0": p0}
 
 
 def get(name: str) -> Scene:

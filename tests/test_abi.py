@@ -83,6 +83,8 @@ def test_call_order_errors(L):
     assert b"set_spectrum" in L.hwo_last_error(h)
     assert L.hwo_step_index(h) == 0
     assert L.hwo_record_bytes(h) == 32
+    buf = (C.c_double * 64)()
+    assert L.hwo_read_buckets(h, buf, 64) == hwo.HWO_ESTATE   # before set_spectrum
     ms = C.c_double()
     # only idempotent stages can be re-launched, and only after a step
     for stage in (0, 3, 4, 5):   # params, count, scan, scatter

@@ -157,6 +157,22 @@ def test_batched_scenes_short(name, steps):
     say(f"  err={e}")
 
 
+def test_paper_default_scene_short():
+    """The paper's default parameters with equal-energy buckets (every bucket
+    on the matrix-core path, radii 4.7-50 cells), Mitsuyasu spreading and
+    fetch-dependent gamma: 40 steps, integer state bit-exact, heights."""
+    s = scenes.p0()
+    g, o = make(s, compact=True, batched=True)
+    # the library's FP64 bucket table equals the oracle's bit for bit
+    want = np.array([[o.bucket(i)[k] for k in ("w", "dw", "r", "c")] for i in range(o.nb)])
+    assert np.array_equal(g.buckets(), want)
+    g.step(40)
+    o.step(40)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s)
+    say(f"p0 err={e}")
+
+
 def test_c4_far_anchor():
     s = scenes.c4()
     g, o = make(s)
@@ -167,7 +183,7 @@ def test_c4_far_anchor():
     say(f"c4 err={e}")
 
 
-@pytest.mark.parametrize("name,frames", [("c3", 900), ("c5", 900)])
+@pytest.mark.parametrize("name,frames", [("c3", 900), ("c5", 900), ("p0", 1200)])
 def test_full_size_state(name, frames):
     """The benchmark's state: frame 900 of the batched scenes in the timed
     launch configuration (16-byte records, one launch per stage, graph

@@ -4,6 +4,7 @@ Each test checks the oracle against something other than itself: a closed
 form, an invariant of the paper's equations, or an independent library
 implementation.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -255,3 +256,43 @@ def test_subdivision_ages_closed_form():
         assert sp(T) > 0.5 * b["r"]
         if T > 0:
             assert sp(T - 1) <= 0.5 * b["r"]
+
+
+def test_equal_energy_buckets():
+    """Sec 3.3: the sampling band [0.5 w_p, 2.5 w_p] is cut into N_omega
+    buckets of equal energy.  The edges are rebuilt from each bucket's w_i
+    (geometric mean of its edges) and dw_i; they must tile the band exactly,
+    and every bucket must hold 1/N of the band's integral of S_J, measured with
+    an independent adaptive quadrature."""
+    s = scenes.p0()
+    o = oracle.Oracle(s)
+    wp = o.spectrum_consts()["wp"]
+    nb = s.spectrum.n_buckets
+    edges = []
+    for i in range(nb):
+        b = o.bucket(i)
+        hi = 0.5 * (b["dw"] + math.sqrt(b["dw"] ** 2 + 4.0 * b["w"] ** 2))
+        edges.append((hi - b["dw"], hi))
+    # bucket 0 holds the highest frequencies (shortest waves); buckets are contiguous
+    for i in range(nb - 1):
+        assert edges[i][0] == pytest.approx(edges[i + 1][1], rel=1e-12)
+        assert o.bucket(i)["w"] > o.bucket(i + 1)["w"]
+    assert edges[0][1] == pytest.approx(2.5 * wp, rel=1e-12)
+    assert edges[-1][0] == pytest.approx(0.5 * wp, rel=1e-12)
+    opts = dict(epsabs=0.0, epsrel=1e-12, limit=200)
+    total = integrate.quad(o.jonswap, 0.5 * wp, 2.5 * wp, points=[wp], **opts)[0]
+    for lo, hi in edges:
+        e = integrate.quad(o.jonswap, lo, hi, points=[wp] if lo < wp < hi else None, **opts)[0]
+        assert e == pytest.approx(total / nb, rel=1e-7), (lo, hi)
+    # equal energy with the importance-sampled amplitude: A^2 ~ S_J(w_i) dw_i
+    # differs between buckets only by how well S_J(w_i) dw_i approximates the
+    # bucket integral, which is tight away from the steep low-frequency edge
+    A = [o.patch_bucket(0, i)["A"] for i in range(nb - 1)]
+    assert max(A) / min(A) < 1.05
+
+
+def test_bucket_mode_validation():
+    s = scenes.p0()
+    bad = s.replace(spectrum=dataclasses.replace(s.spectrum, bucket_mode=2))
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(bad)
