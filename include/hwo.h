@@ -85,6 +85,11 @@ typedef struct {
     int32_t bucket_mode;    /* 0: n_buckets log-spaced wavelength buckets over
                                [lambda_min, lambda_max]; 1: equal-energy buckets
                                over [0.5 w_p, 2.5 w_p] (Sec 3.3), lambda range unused */
+    int32_t dir_mode;       /* 0: boundary directions by inverse CDF of Dir, equal
+                               amplitudes; 1: stratified groups (Sec 3.3) -- the m-th
+                               particle of a side-pair stream takes sector m mod N_theta
+                               (N_theta = eta, a whole number), amplitude from
+                               S(w_i, theta) */
 } hwo_spectrum;
 
 typedef struct {
@@ -112,7 +117,9 @@ const char *hwo_last_error(const hwo_ocean *o);
 /* Spectrum, buckets, direction tables, h0(k) and twiddles (FP64 on the GPU,
  * stored FP32).  Once per handle, before add_patch / add_source. */
 int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp);
-/* Add a patch (max 127); *id receives its index. */
+/* Add a patch (max 127); *id receives its index.  HWO_EINVAL for a bad size or
+ * dx, and, with dir_mode 1, for an effective eta that is not a whole number in
+ * 1..10368 (one direction code per particle at most). */
 int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id);
 /* Add a moving source (max 127) emitting into patch src->patch. */
 int hwo_add_source(hwo_ocean *o, const hwo_source *s, int32_t *id);

@@ -53,7 +53,7 @@ def lib():
         "orc_create": (vp, [i32, dbl, dbl, dbl, u64]),
         "orc_destroy": (None, [vp]),
         "orc_error": (C.c_char_p, [vp]),
-        "orc_set_spectrum": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, i32, dbl, dbl, dbl, i32, dbl, i32, i32]),
+        "orc_set_spectrum": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, i32, dbl, dbl, dbl, i32, dbl, i32, i32, i32]),
         "orc_add_patch": (C.c_int, [vp, dbl, dbl, i32, i32, dbl, dbl, dbl, i32]),
         "orc_add_source": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32]),
         "orc_set_bins": (C.c_int, [vp, P(i32)]),
@@ -156,7 +156,7 @@ class Oracle:
         self._check(self.L.orc_set_spectrum(h, sp.U10, sp.fetch, sp.gamma, sp.spread_s, sp.wind_dir,
                                             sp.n_buckets, sp.lambda_min, sp.lambda_max, sp.eta,
                                             sp.max_level, sp.subdiv_frac, sp.h0_mode,
-                                            sp.bucket_mode))
+                                            sp.bucket_mode, sp.dir_mode))
         self.nb = sp.n_buckets
         for p in scene.patches:
             self._check(self.L.orc_add_patch(h, p.anchor_x, p.anchor_y, p.nx, p.ny, p.dx, p.eta,

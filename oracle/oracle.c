@@ -81,7 +81,7 @@ struct orc_ocean {
     uint64_t seed;
     int have_spec, stepped, bins_set;
     double U10, fetch, gamma, s_const, wind_dir, alpha, wp, eta, subdiv_frac;
-    int32_t nb, lmax, h0_mode, wind_code;
+    int32_t nb, lmax, h0_mode, wind_code, dir_mode;
     double lam_min, lam_max;
     double w[MAXB], dw[MAXB], r[MAXB], c[MAXB], lam[MAXB];
     int64_t margin[MAXB];
@@ -259,11 +259,12 @@ static void equal_energy_edges(const orc_ocean *o, int n, double *e) {
 int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, double spread_s,
                      double wind_dir, int32_t n_buckets, double lambda_min, double lambda_max,
                      double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode,
-                     int32_t bucket_mode) {
+                     int32_t bucket_mode, int32_t dir_mode) {
     if (o->have_spec) return fail(o, "spectrum already set");
     if (!(U10 > 0) || !(fetch > 0)) return fail(o, "U10 and fetch must be positive");
     if (n_buckets < 1 || n_buckets > MAXB) return fail(o, "n_buckets out of range");
     if (bucket_mode != 0 && bucket_mode != 1) return fail(o, "bucket_mode must be 0 or 1");
+    if (dir_mode != 0 && dir_mode != 1) return fail(o, "dir_mode must be 0 or 1");
     if (bucket_mode == 0 && (!(lambda_min > 0) || !(lambda_max > lambda_min))) return fail(o, "bad lambda range");
     if (!(eta > 0)) return fail(o, "eta must be positive");
     if (max_level < 0 || max_level > LMAX_CAP) return fail(o, "max_level out of range");
@@ -277,6 +278,7 @@ int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, doubl
     o->lmax = max_level;
     o->subdiv_frac = subdiv_frac;
     o->h0_mode = h0_mode;
+    o->dir_mode = dir_mode;
     o->nb = n_buckets;
     o->lam_min = lambda_min;
     o->lam_max = lambda_max;
@@ -395,6 +397,8 @@ int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, do
     p->dx = dx;
     p->dxu = (int64_t)dxu;
     p->eta = (eta > 0.0) ? eta : o->eta;
+    if (o->dir_mode == 1 && (p->eta != floor(p->eta) || p->eta > (double)NCODE))
+        return fail(o, "stratified directions need a whole number of particles per group");
     double rmax = o->r[o->nb - 1];
     double lmin = (double)(nx < ny ? nx : ny) * dx / 4.0;
     p->band = (band > 0.0) ? band : (rmax < lmin ? rmax : lmin);
@@ -641,12 +645,25 @@ static int step_once(orc_ocean *o) {
                     uint64_t key[2] = {o->seed, STREAM_INJECT};
                     uint64_t u[4];
                     orc_philox4x64(ctr, key, u);
-                    uint64_t t = mulhi64(u[0], (uint64_t)o->Q[i]);
-                    int b = 0;
-                    while (!((int64_t)t < o->cdf[i][b])) ++b;
                     prt_t q;
                     memset(&q, 0, sizeof q);
-                    q.code = o->codes[b];
+                    if (o->dir_mode == 0) {
+                        /* inverse CDF of Dir over the 64 direction bins */
+                        uint64_t t = mulhi64(u[0], (uint64_t)o->Q[i]);
+                        int b = 0;
+                        while (!((int64_t)t < o->cdf[i][b])) ++b;
+                        q.code = o->codes[b];
+                    } else {
+                        /* stratified group (Sec 3.3): the m-th particle of this
+                         * side pair's stream takes sector m mod N_theta of
+                         * [-pi, pi) around the wind, uniformly inside it */
+                        int64_t nth = (int64_t)pt->eta;
+                        int64_t m = cum_count(R, n - 1) + j;
+                        int64_t s = m % nth;
+                        int64_t lo = s * NCODE / nth, hi = (s + 1) * NCODE / nth;
+                        q.code = (int32_t)pmod((int64_t)o->wind_code + NCODE / 2 + lo +
+                                                   (int64_t)mulhi64(u[0], (uint64_t)(hi - lo)), NCODE);
+                    }
                     const int64_t *v = &o->V[((size_t)i * NCODE + q.code) * 2];
                     if (pair == 0) {
                         q.ox = (v[0] > 0) ? pt->wx * pt->dxu : (pt->wx + pt->nx) * pt->dxu;
@@ -941,7 +958,14 @@ int orc_background(orc_ocean *o, double *H) { return orc_background_at(o, (doubl
 
 /* ---------------------------------------------------------------- splat */
 static double amplitude(const orc_ocean *o, const prt_t *q) {
-    if (q->kind == 0) return o->pt[q->patch].A[q->bucket];
+    if (q->kind == 0) {
+        const patch_t *pt = &o->pt[q->patch];
+        if (o->dir_mode == 0) return pt->A[q->bucket];
+        /* Eq "A" with the particle's own direction and dtheta = 2 pi / N_theta:
+         * A^2 = 2 S_J(w_i) Dir(theta) dw_i dtheta = A_{p,i}^2 * 2 pi Dir(theta) */
+        double th = 2.0 * M_PI * (double)q->code / (double)NCODE - o->wind_dir;
+        return pt->A[q->bucket] * sqrt(2.0 * M_PI * dir_s(orc_spread(o, o->w[q->bucket]), th));
+    }
     const src_t *s = &o->sr[q->src];
     return s->B * s->m[q->slot] / (double)ipow3(q->level);
 }

@@ -31,7 +31,7 @@ const char *orc_error(const orc_ocean *o);
 int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, double spread_s,
                      double wind_dir, int32_t n_buckets, double lambda_min, double lambda_max,
                      double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode,
-                     int32_t bucket_mode);
+                     int32_t bucket_mode, int32_t dir_mode);
 int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, double dx,
                   double eta, double band, int32_t follow);
 int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,

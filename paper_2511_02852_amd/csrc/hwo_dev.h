@@ -79,6 +79,7 @@ struct PatchDev {
   float inv_band;
   int32_t bin_lo, bin_hi;      // bins of this patch in the global histogram
   int32_t tile0, ntx, nty;     // splat output tiles
+  int32_t ntheta;              // directions per group (stratified mode)
   int32_t src_lo, src_hi;      // range in the patch-sorted source list
   int64_t cell0;               // offset of this patch in the height buffers
   float A[kMaxBuckets];        // boundary amplitude per bucket
@@ -118,6 +119,7 @@ enum { CNT_INJ = 0, CNT_EMIT, CNT_SUB, CNT_DIED, CNT_NUM };
 struct Dev {
   int32_t np, ns, nb, N, cap, nbins, ntiles, compact, lmax;
   int32_t n_inj_slots;         // np * nb * 2
+  int32_t wind_code;           // wind direction in direction-code units
   double g, dt, L, dxf;
   uint64_t seed;
   const PatchDev *patches;
@@ -125,6 +127,7 @@ struct Dev {
   const int32_t *src_order;    // sources sorted by patch
   const int2 *V;               // [nb][kNCode] velocity per step
   const float2 *UC;            // [kNCode] unit direction
+  const float *afac;           // [nb][kNCode] stratified-direction amplitude factor sqrt(2 pi Dir); null: inverse-CDF mode
   const uint32_t *cdf;         // [nb][64] inclusive integer CDF
   const uint32_t *cdfQ;        // [nb] totals
   const int32_t *codes;        // [64] direction code of each bin
@@ -236,12 +239,14 @@ template <> struct RecIO<RecCompact> {
 };
 
 // Amplitude of a particle: boundary particles carry the patch/bucket
-// amplitude; ring particles B * m_slot / 3^level.
+// amplitude (times the direction factor in stratified mode); ring particles
+// B * m_slot / 3^level.
 template <class Rec>
 __device__ inline float particle_amp(const Dev &d, const Part &p) {
   if (RecIO<Rec>::kHasAmp) return p.amp;
   uint32_t m = p.meta;
-  if (m_kind(m) == 0) return d.patches[m_patch(m)].A[m_bucket(m)];
+  if (m_kind(m) == 0)
+    return d.patches[m_patch(m)].A[m_bucket(m)] * (d.afac ? d.afac[m_bucket(m) * kNCode + p.code] : 1.f);
   const SourceDev &s = d.sources[m_src(m)];
   const float inv3[5] = {1.f, 1.f / 3.f, 1.f / 9.f, 1.f / 27.f, 1.f / 81.f};
   return s.B * d.ring_m[s.ring0 + m_slot(m)] * inv3[m_level(m)];

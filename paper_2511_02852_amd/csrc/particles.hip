@@ -300,13 +300,26 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       const int pair = slot & 1;
       uint64_t c[4] = {(uint64_t)pid, (uint64_t)(bkt * 2 + pair), (uint64_t)n, (uint64_t)j};
       philox4x64(c, d.seed, kStreamInject);
-      const uint32_t Q = d.cdfQ[bkt];
-      const uint32_t t = (uint32_t)__umul64hi(c[0], (uint64_t)Q);
-      const uint32_t *cdf = s_cdf + bkt * kDirBins;
-      int b = 0;   // smallest bin with t < cdf[b]
-      for (int step = 32; step > 0; step >>= 1)
-        if (cdf[b + step - 1] <= t) b += step;
-      const int code = d.codes[b];
+      const PatchDev &P0 = d.patches[pid];
+      int code;
+      if (!d.afac) {
+        // inverse CDF of Dir over the 64 direction bins
+        const uint32_t Q = d.cdfQ[bkt];
+        const uint32_t t = (uint32_t)__umul64hi(c[0], (uint64_t)Q);
+        const uint32_t *cdf = s_cdf + bkt * kDirBins;
+        int b = 0;   // smallest bin with t < cdf[b]
+        for (int step = 32; step > 0; step >>= 1)
+          if (cdf[b + step - 1] <= t) b += step;
+        code = d.codes[b];
+      } else {
+        // stratified group: the m-th particle of this side pair's stream
+        // takes sector m mod N_theta around the wind, uniformly inside it
+        const int64_t nth = P0.ntheta;
+        const int64_t m = cum_count(pair ? P0.Ry[bkt] : P0.Rx[bkt], n - 1) + j;
+        const int64_t sct = m % nth;
+        const int64_t lo = sct * kNCode / nth, hi = (sct + 1) * kNCode / nth;
+        code = (int)((d.wind_code + kNCode / 2 + lo + (int64_t)__umul64hi(c[0], (uint64_t)(hi - lo))) % kNCode);
+      }
       const PatchDev &P = d.patches[pid];
       const StepPatch W = d.sp[pid];
       const int2 v = d.V[bkt * kNCode + code];
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       q.age = 0;
       q.code = code;
       q.meta = pack_meta(0, 0, bkt, pid, kNoSource, 0);
-      q.amp = P.A[bkt];
+      q.amp = P.A[bkt] * (d.afac ? d.afac[bkt * kNCode + code] : 1.f);
       o[0] = q;
       nout = 1;
     } else if (k < total) {

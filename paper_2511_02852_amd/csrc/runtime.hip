@@ -68,6 +68,8 @@ struct hwo_ocean {
   int32_t margin[kMaxBuckets];
   std::vector<uint32_t> qw;        // [nb][64]
   std::vector<int32_t> codes;      // [64]
+  int32_t wind_code = 0;           // wind direction in direction-code units
+  std::vector<float> afac;         // [nb][kNCode] sqrt(2 pi Dir); stratified directions only
   std::vector<int2> V;             // [nb][kNCode]
   std::vector<float2> UC;          // [kNCode]
   // scene tables
@@ -228,6 +230,7 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   if (!(sp->U10 > 0) || !(sp->fetch > 0)) return o->fail(HWO_EINVAL, "U10 and fetch must be positive");
   if (sp->n_buckets < 1 || sp->n_buckets > kMaxBuckets) return o->fail(HWO_EINVAL, "n_buckets out of range");
   if (sp->bucket_mode != 0 && sp->bucket_mode != 1) return o->fail(HWO_EINVAL, "bucket_mode must be 0 or 1");
+  if (sp->dir_mode != 0 && sp->dir_mode != 1) return o->fail(HWO_EINVAL, "dir_mode must be 0 or 1");
   if (sp->bucket_mode == 0 && (!(sp->lambda_min > 0) || !(sp->lambda_max > sp->lambda_min)))
     return o->fail(HWO_EINVAL, "bad lambda range");
   if (!(sp->eta > 0)) return o->fail(HWO_EINVAL, "eta must be positive");
@@ -283,6 +286,22 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
       tot += qb;
     }
     if (tot <= 0 || tot >= ((int64_t)1 << 32)) return o->fail(HWO_EINVAL, "degenerate direction distribution");
+  }
+  o->wind_code = wind_code;
+  // Stratified directions: a particle of bucket i heading along theta carries
+  // A_i * sqrt(2 pi Dir(theta - wind)), so that over a group of N_theta equal
+  // sectors its squared amplitude sums to the bucket's share S(w_i) dw_i (Eq 7
+  // with dtheta = 2 pi / N_theta).
+  o->afac.clear();
+  if (sp->dir_mode == 1) {
+    o->afac.resize((size_t)o->nb * kNCode);
+    for (int i = 0; i < o->nb; ++i) {
+      double s = spread_h(o, o->w[i]);
+      for (int code = 0; code < kNCode; ++code) {
+        double th = 2.0 * M_PI * (double)code / (double)kNCode - sp->wind_dir;
+        o->afac[(size_t)i * kNCode + code] = (float)sqrt(2.0 * M_PI * dir_h(s, th));
+      }
+    }
   }
   // velocity per step and unit vectors
   o->V.resize((size_t)o->nb * kNCode);
@@ -342,6 +361,9 @@ int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id) {
     return o->fail(HWO_EINVAL, "dx must be an even multiple of 2^-20 m");
   if ((double)p->nx * dxu > 1.5e9 || (double)p->ny * dxu > 1.5e9) return o->fail(HWO_EINVAL, "patch too large");
   if (p->follow < -1) return o->fail(HWO_EINVAL, "bad follow id");
+  const double eta = (p->eta > 0.0) ? p->eta : o->sp.eta;
+  if (o->sp.dir_mode == 1 && (eta != floor(eta) || eta > (double)kNCode))
+    return o->fail(HWO_EINVAL, "stratified directions need a whole number of particles per group");
   if (id) *id = (int32_t)o->patches.size();
   o->patches.push_back(*p);
   return HWO_OK;
@@ -400,6 +422,9 @@ static int build_scene_tables(hwo_ocean *o) {
     P.dxu = (int32_t)(hp.dx * kUnit);
     P.follow = hp.follow;
     const double eta = (hp.eta > 0.0) ? hp.eta : o->sp.eta;
+    if (o->sp.dir_mode == 1 && (eta != floor(eta) || eta > (double)kNCode))
+      return o->fail(HWO_EINVAL, "stratified directions need a whole number of particles per group");
+    P.ntheta = (int32_t)eta;
     const double rmax = o->r[nb - 1];
     const double lmin = (double)(hp.nx < hp.ny ? hp.nx : hp.ny) * hp.dx / 4.0;
     P.band = (float)((hp.blend_band > 0.0) ? hp.blend_band : (rmax < lmin ? rmax : lmin));
@@ -568,6 +593,8 @@ static int finalize(hwo_ocean *o) {
   d.cdf = o->cdf;
   d.cdfQ = o->cdfQ;
   d.codes = upload(o, o->codes, &rc);
+  d.afac = o->afac.empty() ? nullptr : upload(o, o->afac, &rc);
+  d.wind_code = o->wind_code;
   std::vector<float> br(nb);
   std::vector<int32_t> bm(nb);
   for (int i = 0; i < nb; ++i) {

@@ -69,7 +69,8 @@ __device__ __forceinline__ bool load_item(const Dev &d, const Rec &r, int64_t n,
   const int64_t py = (int64_t)q.oy + (((int64_t)q.age * v.y) >> 12);
   cx = (float)(px - T.X0) * T.inv_dxu;
   cy = (float)(py - T.Y0) * T.inv_dxu;
-  A = (RecIO<Rec>::kHasAmp || m_kind(q.meta) != 0) ? particle_amp<Rec>(d, q) : T.Ab;
+  A = (RecIO<Rec>::kHasAmp || m_kind(q.meta) != 0) ? particle_amp<Rec>(d, q)
+                                                    : T.Ab * (d.afac ? d.afac[b * kNCode + q.code] : 1.f);
   u = d.UC[q.code];
   return true;
 }

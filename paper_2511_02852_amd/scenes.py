@@ -41,6 +41,8 @@ class Spectrum:
     h0_mode: 0 Gaussian h0 amplitudes, 1 unit-modulus (deterministic variance).
     bucket_mode: 0 log-spaced wavelength buckets over [lambda_min, lambda_max];
       1 equal-energy buckets over [0.5 w_p, 2.5 w_p] (the lambda range is unused).
+    dir_mode: 0 directions by inverse CDF of Dir, equal amplitudes; 1 stratified
+      groups of eta (= N_theta, a whole number) directions, amplitude from S(w, theta).
     """
     U10: float = 10.0
     fetch: float = 100e3
@@ -55,6 +57,7 @@ class Spectrum:
     subdiv_frac: float = 0.5
     h0_mode: int = 0
     bucket_mode: int = 0
+    dir_mode: int = 0
 
 
 @dataclass

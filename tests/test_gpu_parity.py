@@ -173,6 +173,25 @@ def test_paper_default_scene_short():
     say(f"p0 err={e}")
 
 
+@pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "plain"),
+                                             ("c2", 60, "batched"), ("p0", 40, "batched")])
+def test_stratified_directions(name, steps, form):
+    """Stratified boundary directions (a group of N_theta = eta particles
+    visits every sector, amplitude from S(w, theta)): integer state bit-exact
+    and heights, in the wide and the compact record forms."""
+    import dataclasses
+    s = scenes.get(name)
+    s = s.replace(spectrum=dataclasses.replace(s.spectrum, dir_mode=1, wind_dir=0.7))
+    kw = dict(compact=True, batched=True) if form == "batched" else {}
+    say(f"stratified {name} {form} {steps} steps")
+    g, o = make(s, **kw)
+    g.step(steps)
+    o.step(steps)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s)
+    say(f"stratified {name} {form} err={e}")
+
+
 def test_c4_far_anchor():
     s = scenes.c4()
     g, o = make(s)

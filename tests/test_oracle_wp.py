@@ -1,4 +1,5 @@
 """Pins of the oracle's wave-particle branch and blend (CPU only)."""
+import dataclasses
 import math
 
 import numpy as np
@@ -331,3 +332,99 @@ def test_seek_splat_and_blend_reproduce_patch_maps():
     assert np.allclose(b.blend(0, H, raw2), bl, rtol=0, atol=1e-12 * max(1.0, np.abs(bl).max()))
     with pytest.raises(oracle.OracleError):
         a.seek(20)   # holds particles
+
+
+# ---------------------------------------------------------------- stratified directions
+def strat_scene(wind_dir, spread_s=-1.0, eta=16.0, nx=64):
+    """Two equal-energy buckets of the paper's default spectrum with Mitsuyasu
+    spreading (a different s per bucket), stratified directions."""
+    sp = scenes.Spectrum(U10=5.0, fetch=10e3, gamma=0.0, spread_s=spread_s, wind_dir=wind_dir,
+                         n_buckets=2, eta=eta, bucket_mode=1, dir_mode=1)
+    return scenes.Scene(name="strat", fft_n=64, fft_L=256.0, seed=5, steps=0, spectrum=sp,
+                        patches=[scenes.Patch(anchor_x=0.0, anchor_y=0.0, nx=nx, ny=nx,
+                                              dx=100.0 / 512)],
+                        bins=[16, 16])
+
+
+def wind_code(wind_dir):
+    return int(round(wind_dir * oracle.NCODE / (2 * math.pi))) % oracle.NCODE
+
+
+def test_stratified_groups_cover_every_sector():
+    """Sec 3.3: a group holds N_theta particles spanning all directions with
+    dtheta = 2 pi / N_theta.  The injected stream of each (bucket, side pair)
+    visits the N_theta sectors round robin, so over any run each sector holds
+    floor or ceil of M / N_theta of that stream's M particles; inside its
+    sector a direction is uniform."""
+    wd = 0.7
+    s = strat_scene(wd, eta=16.0, nx=512)
+    o = oracle.Oracle(s)
+    nsteps = 40
+    o.step(nsteps)
+    P = o.particles()
+    c = o.counts(0)
+    nth = 16
+    frac = []
+    for b in range(o.nb):
+        M = [sum(o.inject_count(0, b, pair, n) for n in range(1, nsteps + 1)) for pair in (0, 1)]
+        assert c[b, 1] == sum(M) and sum(M) > 10 * nth
+        died = int(c[b, 4])
+        rel = (P[P[:, 1] == b, 4] - wind_code(wd) - oracle.NCODE // 2) % oracle.NCODE
+        sector = rel * nth // oracle.NCODE
+        per = np.bincount(sector, minlength=nth)
+        lo = sum(m // nth for m in M) - died
+        hi = sum(-(-m // nth) for m in M)
+        assert per.min() >= lo and per.max() <= hi, (b, per, M, died)
+        lo_code = sector * oracle.NCODE // nth
+        hi_code = (sector + 1) * oracle.NCODE // nth
+        frac.append((rel - lo_code) / (hi_code - lo_code))
+    frac = np.concatenate(frac)
+    assert frac.min() >= 0.0 and frac.max() < 1.0
+    assert stats.kstest(frac, "uniform").pvalue > 1e-4
+
+
+def test_stratified_amplitude_follows_directional_spectrum():
+    """Eq 7 with dtheta = 2 pi / N_theta: relative to the equal-amplitude
+    particle of the inverse-CDF mode, a particle heading theta carries
+    sqrt(2 pi Dir(theta - wind)).  Pinned by single-particle splats against
+    what Dir must satisfy: it integrates to one over a turn (so the squared
+    factor averages to one over the directions), it peaks along the wind, it
+    is even about the wind and it vanishes against it (cos-2s, Eq 5)."""
+    k0 = 1008
+    wd = 2 * math.pi * k0 / oracle.NCODE
+    s1 = strat_scene(wd)
+    s0 = s1.replace(spectrum=dataclasses.replace(s1.spectrum, dir_mode=0))
+    o1, o0 = oracle.Oracle(s1), oracle.Oracle(s0)
+    c = (0.5 * 64 * 100.0 / 512) * UNIT
+    stride = 16
+    codes = np.arange(0, oracle.NCODE, stride)
+    def factor(b, q):
+        one = np.array([rec(int(c), int(c), int(q), bucket=b)])
+        ref = o0.splat(0, one)
+        j = np.unravel_index(np.argmax(np.abs(ref)), ref.shape)
+        return o1.splat(0, one)[j] / ref[j]
+
+    for b in range(2):
+        ratio = np.array([factor(b, q) for q in codes])
+        assert np.all(ratio >= 0.0)
+        # periodic trapezoid rule over a smooth periodic integrand
+        assert np.mean(ratio ** 2) == pytest.approx(1.0, abs=1e-9)
+        assert codes[np.argmax(ratio)] == k0
+        opp = (k0 + oracle.NCODE // 2) % oracle.NCODE
+        assert ratio[codes == opp][0] == pytest.approx(0.0, abs=1e-12)
+        for d in (stride, 7 * stride, 100 * stride):
+            a = ratio[codes == (k0 + d) % oracle.NCODE][0]
+            bb = ratio[codes == (k0 - d) % oracle.NCODE][0]
+            assert a == pytest.approx(bb, rel=1e-9)
+    # the Mitsuyasu exponent differs between the buckets (s peaks at w_p)
+    assert o1.spread(o1.bucket(0)["w"]) != o1.spread(o1.bucket(1)["w"])
+
+
+def test_stratified_needs_whole_group():
+    s = strat_scene(0.0, eta=16.5)
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(s)
+    s = strat_scene(0.0, eta=16.0)
+    s.patches[0].eta = 3.25
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(s)
