@@ -90,6 +90,11 @@ typedef struct {
                                particle of a side-pair stream takes sector m mod N_theta
                                (N_theta = eta, a whole number), amplitude from
                                S(w_i, theta) */
+    int32_t flux_mode;      /* 0: each side pair injects the group count of Eq 18;
+                               1: obliquity-weighted -- a pair's count is scaled by
+                               the mean |cos| of the angle between the wave and the
+                               side normal under Dir, and its directions are drawn
+                               from Dir |cos|.  Needs dir_mode 0. */
 } hwo_spectrum;
 
 typedef struct {

@@ -53,7 +53,7 @@ def lib():
         "orc_create": (vp, [i32, dbl, dbl, dbl, u64]),
         "orc_destroy": (None, [vp]),
         "orc_error": (C.c_char_p, [vp]),
-        "orc_set_spectrum": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, i32, dbl, dbl, dbl, i32, dbl, i32, i32, i32]),
+        "orc_set_spectrum": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, i32, dbl, dbl, dbl, i32, dbl, i32, i32, i32, i32]),
         "orc_add_patch": (C.c_int, [vp, dbl, dbl, i32, i32, dbl, dbl, dbl, i32]),
         "orc_add_source": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32]),
         "orc_set_bins": (C.c_int, [vp, P(i32)]),
@@ -74,7 +74,7 @@ def lib():
         "orc_spectrum_consts": (C.c_int, [vp, P(dbl)]),
         "orc_bucket": (C.c_int, [vp, i32, P(dbl)]),
         "orc_patch_bucket": (C.c_int, [vp, i32, i32, P(dbl)]),
-        "orc_dir_table": (C.c_int, [vp, i32, P(i64), P(i64), P(i64)]),
+        "orc_dir_table": (C.c_int, [vp, i32, i32, P(i64), P(i64), P(i64)]),
         "orc_velocity": (C.c_int, [vp, i32, i32, P(i64)]),
         "orc_source_info": (C.c_int, [vp, i32, P(dbl)]),
         "orc_inject_count": (i64, [vp, i32, i32, i32, i64]),
@@ -156,7 +156,7 @@ class Oracle:
         self._check(self.L.orc_set_spectrum(h, sp.U10, sp.fetch, sp.gamma, sp.spread_s, sp.wind_dir,
                                             sp.n_buckets, sp.lambda_min, sp.lambda_max, sp.eta,
                                             sp.max_level, sp.subdiv_frac, sp.h0_mode,
-                                            sp.bucket_mode, sp.dir_mode))
+                                            sp.bucket_mode, sp.dir_mode, sp.flux_mode))
         self.nb = sp.n_buckets
         for p in scene.patches:
             self._check(self.L.orc_add_patch(h, p.anchor_x, p.anchor_y, p.nx, p.ny, p.dx, p.eta,
@@ -266,11 +266,11 @@ class Oracle:
         self._check(self.L.orc_patch_bucket(self.h, p, i, _p(out, C.c_double)))
         return dict(A=out[0], Rx=int(out[1]), Ry=int(out[2]), band=out[3], eta=out[4])
 
-    def dir_table(self, i: int):
+    def dir_table(self, i: int, pair: int = 0):
         q = np.zeros(NDIR, dtype=np.int64)
         cdf = np.zeros(NDIR, dtype=np.int64)
         codes = np.zeros(NDIR, dtype=np.int64)
-        self._check(self.L.orc_dir_table(self.h, i, _p(q, C.c_int64), _p(cdf, C.c_int64),
+        self._check(self.L.orc_dir_table(self.h, i, pair, _p(q, C.c_int64), _p(cdf, C.c_int64),
                                          _p(codes, C.c_int64)))
         return q, cdf, codes
 

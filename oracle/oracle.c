@@ -81,11 +81,13 @@ struct orc_ocean {
     uint64_t seed;
     int have_spec, stepped, bins_set;
     double U10, fetch, gamma, s_const, wind_dir, alpha, wp, eta, subdiv_frac;
-    int32_t nb, lmax, h0_mode, wind_code, dir_mode;
+    int32_t nb, lmax, h0_mode, wind_code, dir_mode, flux_mode;
     double lam_min, lam_max;
     double w[MAXB], dw[MAXB], r[MAXB], c[MAXB], lam[MAXB];
     int64_t margin[MAXB];
-    int64_t q[MAXB][NDIR], cdf[MAXB][NDIR], Q[MAXB];
+    /* direction weights per bucket and side pair (0: sides normal to x) */
+    int64_t q[MAXB][2][NDIR], cdf[MAXB][2][NDIR], Q[MAXB][2];
+    double kappa[MAXB][2];   /* flux factor of each side pair; 1 when flux_mode is 0 */
     int32_t codes[NDIR];
     int64_t *V;                 /* [nb][NCODE][2] */
     double *h0re, *h0im;        /* [N][N], row = y index */
@@ -259,12 +261,14 @@ static void equal_energy_edges(const orc_ocean *o, int n, double *e) {
 int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, double spread_s,
                      double wind_dir, int32_t n_buckets, double lambda_min, double lambda_max,
                      double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode,
-                     int32_t bucket_mode, int32_t dir_mode) {
+                     int32_t bucket_mode, int32_t dir_mode, int32_t flux_mode) {
     if (o->have_spec) return fail(o, "spectrum already set");
     if (!(U10 > 0) || !(fetch > 0)) return fail(o, "U10 and fetch must be positive");
     if (n_buckets < 1 || n_buckets > MAXB) return fail(o, "n_buckets out of range");
     if (bucket_mode != 0 && bucket_mode != 1) return fail(o, "bucket_mode must be 0 or 1");
     if (dir_mode != 0 && dir_mode != 1) return fail(o, "dir_mode must be 0 or 1");
+    if (flux_mode != 0 && flux_mode != 1) return fail(o, "flux_mode must be 0 or 1");
+    if (flux_mode == 1 && dir_mode != 0) return fail(o, "obliquity-weighted injection needs dir_mode 0");
     if (bucket_mode == 0 && (!(lambda_min > 0) || !(lambda_max > lambda_min))) return fail(o, "bad lambda range");
     if (!(eta > 0)) return fail(o, "eta must be positive");
     if (max_level < 0 || max_level > LMAX_CAP) return fail(o, "max_level out of range");
@@ -279,6 +283,7 @@ int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, doubl
     o->subdiv_frac = subdiv_frac;
     o->h0_mode = h0_mode;
     o->dir_mode = dir_mode;
+    o->flux_mode = flux_mode;
     o->nb = n_buckets;
     o->lam_min = lambda_min;
     o->lam_max = lambda_max;
@@ -320,20 +325,33 @@ int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, doubl
                                     (int64_t)(2 * b + 1) * (NCODE / (2 * NDIR)), NCODE);
 
     /* Integer inverse-CDF weights of Dir per bucket (Sec 4.2: directions are
-     * sampled from the same directional spectrum). */
+     * sampled from the same directional spectrum), one table per side pair.
+     * With obliquity weighting a wave heading phi crosses the sides normal
+     * to x at the rate c |cos phi| (|sin phi| for y), so the pair's directions
+     * follow Dir |cos phi| and its group count (Eq 18) is scaled by the mean
+     * of |cos phi| under Dir, kappa. */
     double dth = 2.0 * M_PI / (double)NDIR;
     for (int i = 0; i < n_buckets; ++i) {
         double s = orc_spread(o, o->w[i]);
-        int64_t acc = 0;
-        for (int b = 0; b < NDIR; ++b) {
-            double th = -M_PI + ((double)b + 0.5) * dth;
-            int64_t qb = llround(dir_s(s, th) * dth * TWO30);
-            o->q[i][b] = qb;
-            acc += qb;
-            o->cdf[i][b] = acc;
+        for (int pair = 0; pair < 2; ++pair) {
+            int64_t acc = 0;
+            double num = 0.0, den = 0.0;
+            for (int b = 0; b < NDIR; ++b) {
+                double th = -M_PI + ((double)b + 0.5) * dth;
+                double d = dir_s(s, th);
+                double phi = 2.0 * M_PI * (double)o->codes[b] / (double)NCODE;
+                double ob = fabs(pair == 0 ? cos(phi) : sin(phi));
+                num += d * ob;
+                den += d;
+                int64_t qb = llround((flux_mode ? d * ob : d) * dth * TWO30);
+                o->q[i][pair][b] = qb;
+                acc += qb;
+                o->cdf[i][pair][b] = acc;
+            }
+            o->Q[i][pair] = acc;
+            o->kappa[i][pair] = flux_mode ? num / den : 1.0;
+            if (acc <= 0) return fail(o, "empty direction distribution");
         }
-        o->Q[i] = acc;
-        if (acc <= 0) return fail(o, "empty direction distribution");
     }
 
     /* Fixed-point velocity per step, 2^-32 m units. */
@@ -362,11 +380,11 @@ int orc_bucket(const orc_ocean *o, int32_t i, double *out) {
     return 0;
 }
 
-int orc_dir_table(const orc_ocean *o, int32_t i, int64_t *q, int64_t *cdf, int64_t *codes) {
-    if (!o->have_spec || i < 0 || i >= o->nb) return -1;
+int orc_dir_table(const orc_ocean *o, int32_t i, int32_t pair, int64_t *q, int64_t *cdf, int64_t *codes) {
+    if (!o->have_spec || i < 0 || i >= o->nb || pair < 0 || pair > 1) return -1;
     for (int b = 0; b < NDIR; ++b) {
-        q[b] = o->q[i][b];
-        cdf[b] = o->cdf[i][b];
+        q[b] = o->q[i][pair][b];
+        cdf[b] = o->cdf[i][pair][b];
         codes[b] = o->codes[b];
     }
     return 0;
@@ -411,8 +429,8 @@ int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, do
         /* Eq "result_2": groups per step for the pair of sides of length L */
         double gx = 4.0 * Ly * o->dt * w * w * w / (M_PI * M_PI * M_PI * o->g);
         double gy = 4.0 * Lx * o->dt * w * w * w / (M_PI * M_PI * M_PI * o->g);
-        p->Rx[i] = (uint64_t)llround(p->eta * gx * TWO32);
-        p->Ry[i] = (uint64_t)llround(p->eta * gy * TWO32);
+        p->Rx[i] = (uint64_t)llround(p->eta * gx * o->kappa[i][0] * TWO32);
+        p->Ry[i] = (uint64_t)llround(p->eta * gy * o->kappa[i][1] * TWO32);
     }
     o->np += 1;
     return 0;
@@ -649,9 +667,9 @@ static int step_once(orc_ocean *o) {
                     memset(&q, 0, sizeof q);
                     if (o->dir_mode == 0) {
                         /* inverse CDF of Dir over the 64 direction bins */
-                        uint64_t t = mulhi64(u[0], (uint64_t)o->Q[i]);
+                        uint64_t t = mulhi64(u[0], (uint64_t)o->Q[i][pair]);
                         int b = 0;
-                        while (!((int64_t)t < o->cdf[i][b])) ++b;
+                        while (!((int64_t)t < o->cdf[i][pair][b])) ++b;
                         q.code = o->codes[b];
                     } else {
                         /* stratified group (Sec 3.3): the m-th particle of this

@@ -31,7 +31,7 @@ const char *orc_error(const orc_ocean *o);
 int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, double spread_s,
                      double wind_dir, int32_t n_buckets, double lambda_min, double lambda_max,
                      double eta, int32_t max_level, double subdiv_frac, int32_t h0_mode,
-                     int32_t bucket_mode, int32_t dir_mode);
+                     int32_t bucket_mode, int32_t dir_mode, int32_t flux_mode);
 int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, double dx,
                   double eta, double band, int32_t follow);
 int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,
@@ -58,7 +58,9 @@ double orc_spread(const orc_ocean *o, double w);
 int orc_spectrum_consts(const orc_ocean *o, double *out);
 int orc_bucket(const orc_ocean *o, int32_t i, double *out);
 int orc_patch_bucket(const orc_ocean *o, int32_t p, int32_t i, double *out);
-int orc_dir_table(const orc_ocean *o, int32_t i, int64_t *q, int64_t *cdf, int64_t *codes);
+/* Integer direction weights, inclusive CDF and bin codes of bucket i for side
+ * pair `pair` (0: the sides normal to x, 1: normal to y), 64 entries each. */
+int orc_dir_table(const orc_ocean *o, int32_t i, int32_t pair, int64_t *q, int64_t *cdf, int64_t *codes);
 int orc_velocity(const orc_ocean *o, int32_t i, int32_t code, int64_t *v);
 int orc_source_info(const orc_ocean *o, int32_t s, double *out);
 int64_t orc_inject_count(const orc_ocean *o, int32_t p, int32_t i, int32_t pair, int64_t n);

@@ -128,8 +128,8 @@ struct Dev {
   const int2 *V;               // [nb][kNCode] velocity per step
   const float2 *UC;            // [kNCode] unit direction
   const float *afac;           // [nb][kNCode] stratified-direction amplitude factor sqrt(2 pi Dir); null: inverse-CDF mode
-  const uint32_t *cdf;         // [nb][64] inclusive integer CDF
-  const uint32_t *cdfQ;        // [nb] totals
+  const uint32_t *cdf;         // [nb][side pair][64] inclusive integer CDF
+  const uint32_t *cdfQ;        // [nb][side pair] totals
   const int32_t *codes;        // [64] direction code of each bin
   const float *bucket_r;       // [nb] radius (m)
   const int32_t *margin;       // [nb] ceil(2 r 2^20)

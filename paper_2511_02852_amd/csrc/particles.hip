@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   // injection slot offsets and direction CDFs, copied to LDS by the blocks
   // that hold new boundary particles (their searches then stay in LDS)
   __shared__ int32_t s_inj[kMaxInjSlots + 1];
-  __shared__ uint32_t s_cdf[kMaxBuckets * kDirBins];
+  __shared__ uint32_t s_cdf[kMaxBuckets * 2 * kDirBins];
   bool tables = false;
   // the record of the thread's next previous particle is loaded one
   // iteration ahead
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
     if (k + stride < nex) rec_next = Sin[ex0 + k + stride];
     if (!tables && base < nex + ninj && base + kThreads > nex) {   // block-uniform
       for (int i = threadIdx.x; i <= d.n_inj_slots; i += kThreads) s_inj[i] = d.inj_off[i];
-      for (int i = threadIdx.x; i < d.nb * kDirBins; i += kThreads) s_cdf[i] = d.cdf[i];
+      for (int i = threadIdx.x; i < d.nb * 2 * kDirBins; i += kThreads) s_cdf[i] = d.cdf[i];
       __syncthreads();
       tables = true;
     }
@@ -303,10 +303,11 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       const PatchDev &P0 = d.patches[pid];
       int code;
       if (!d.afac) {
-        // inverse CDF of Dir over the 64 direction bins
-        const uint32_t Q = d.cdfQ[bkt];
+        // inverse CDF of Dir (times the obliquity of this side pair, when
+        // weighted) over the 64 direction bins
+        const uint32_t Q = d.cdfQ[bkt * 2 + pair];
         const uint32_t t = (uint32_t)__umul64hi(c[0], (uint64_t)Q);
-        const uint32_t *cdf = s_cdf + bkt * kDirBins;
+        const uint32_t *cdf = s_cdf + (bkt * 2 + pair) * kDirBins;
         int b = 0;   // smallest bin with t < cdf[b]
         for (int step = 32; step > 0; step >>= 1)
           if (cdf[b + step - 1] <= t) b += step;
@@ -484,8 +485,8 @@ __global__ __launch_bounds__(kThreads) void k_scan_b(Dev d, int lo, int hi, int 
 }
 
 // ---------------------------------------------------------------- CDF
-// One wavefront per bucket: inclusive scan of the 64 integer direction
-// weights (exact), giving the inverse-CDF table of Dir for injection.
+// One wavefront per (bucket, side pair): inclusive scan of the 64 integer
+// direction weights (exact), giving the inverse-CDF table for injection.
 __global__ void k_cdf(const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ) {
   const int b = blockIdx.x, lane = threadIdx.x;
   uint32_t v = q[b * kDirBins + lane];
@@ -498,7 +499,7 @@ __global__ void k_cdf(const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ) {
 }
 
 void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, hipStream_t st) {
-  hipLaunchKernelGGL(k_cdf, dim3(d.nb), dim3(64), 0, st, q, cdf, cdfQ);
+  hipLaunchKernelGGL(k_cdf, dim3(d.nb * 2), dim3(64), 0, st, q, cdf, cdfQ);
 }
 
 // ---------------------------------------------------------------- launchers

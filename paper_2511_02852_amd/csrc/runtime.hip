@@ -66,7 +66,8 @@ struct hwo_ocean {
   int nb = 0, lmax = 0;
   double w[kMaxBuckets], dw[kMaxBuckets], r[kMaxBuckets], c[kMaxBuckets];
   int32_t margin[kMaxBuckets];
-  std::vector<uint32_t> qw;        // [nb][64]
+  std::vector<uint32_t> qw;        // [nb][side pair][64]
+  double kappa[kMaxBuckets][2];    // flux factor per side pair (1: the paper's count)
   std::vector<int32_t> codes;      // [64]
   int32_t wind_code = 0;           // wind direction in direction-code units
   std::vector<float> afac;         // [nb][kNCode] sqrt(2 pi Dir); stratified directions only
@@ -231,6 +232,9 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   if (sp->n_buckets < 1 || sp->n_buckets > kMaxBuckets) return o->fail(HWO_EINVAL, "n_buckets out of range");
   if (sp->bucket_mode != 0 && sp->bucket_mode != 1) return o->fail(HWO_EINVAL, "bucket_mode must be 0 or 1");
   if (sp->dir_mode != 0 && sp->dir_mode != 1) return o->fail(HWO_EINVAL, "dir_mode must be 0 or 1");
+  if (sp->flux_mode != 0 && sp->flux_mode != 1) return o->fail(HWO_EINVAL, "flux_mode must be 0 or 1");
+  if (sp->flux_mode == 1 && sp->dir_mode != 0)
+    return o->fail(HWO_EINVAL, "obliquity-weighted injection needs dir_mode 0");
   if (sp->bucket_mode == 0 && (!(sp->lambda_min > 0) || !(sp->lambda_max > sp->lambda_min)))
     return o->fail(HWO_EINVAL, "bad lambda range");
   if (!(sp->eta > 0)) return o->fail(HWO_EINVAL, "eta must be positive");
@@ -274,18 +278,31 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   for (int b = 0; b < kDirBins; ++b)
     o->codes[b] = (int32_t)pmod((int64_t)wind_code + kNCode / 2 + (int64_t)(2 * b + 1) * (kNCode / (2 * kDirBins)),
                                 kNCode);
-  o->qw.assign((size_t)o->nb * kDirBins, 0);
+  // One table per side pair (0: the sides normal to x).  Obliquity weighting
+  // lets a wave heading phi cross the x sides at the rate c |cos phi| (|sin phi|
+  // for y): that pair's directions follow Dir |cos phi| and its group count is
+  // scaled by kappa, the mean of |cos phi| under Dir.
+  o->qw.assign((size_t)o->nb * 2 * kDirBins, 0);
   const double dth = 2.0 * M_PI / (double)kDirBins;
   for (int i = 0; i < o->nb; ++i) {
     double s = spread_h(o, o->w[i]);
-    int64_t tot = 0;
-    for (int b = 0; b < kDirBins; ++b) {
-      double th = -M_PI + ((double)b + 0.5) * dth;
-      int64_t qb = llround(dir_h(s, th) * dth * kTwo30);
-      o->qw[(size_t)i * kDirBins + b] = (uint32_t)qb;
-      tot += qb;
+    for (int pair = 0; pair < 2; ++pair) {
+      int64_t tot = 0;
+      double num = 0.0, den = 0.0;
+      for (int b = 0; b < kDirBins; ++b) {
+        double th = -M_PI + ((double)b + 0.5) * dth;
+        double dv = dir_h(s, th);
+        double phi = 2.0 * M_PI * (double)o->codes[b] / (double)kNCode;
+        double ob = fabs(pair == 0 ? cos(phi) : sin(phi));
+        num += dv * ob;
+        den += dv;
+        int64_t qb = llround((sp->flux_mode ? dv * ob : dv) * dth * kTwo30);
+        o->qw[((size_t)i * 2 + pair) * kDirBins + b] = (uint32_t)qb;
+        tot += qb;
+      }
+      o->kappa[i][pair] = sp->flux_mode ? num / den : 1.0;
+      if (tot <= 0 || tot >= ((int64_t)1 << 32)) return o->fail(HWO_EINVAL, "degenerate direction distribution");
     }
-    if (tot <= 0 || tot >= ((int64_t)1 << 32)) return o->fail(HWO_EINVAL, "degenerate direction distribution");
   }
   o->wind_code = wind_code;
   // Stratified directions: a particle of bucket i heading along theta carries
@@ -331,7 +348,7 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   o->tw = (float2 *)o->alloc(sizeof(float2) * (size_t)N);
   uint32_t *qd = (uint32_t *)o->alloc(sizeof(uint32_t) * o->qw.size());
   o->cdf = (uint32_t *)o->alloc(sizeof(uint32_t) * o->qw.size());
-  o->cdfQ = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)o->nb);
+  o->cdfQ = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)o->nb * 2);
   if (!o->h0T || !o->tw || !qd || !o->cdf || !o->cdfQ) return o->fail(HWO_ENOMEM, "device allocation failed");
   Dev d{};
   d.N = N;
@@ -437,8 +454,8 @@ static int build_scene_tables(hwo_ocean *o) {
       P.A[i] = (float)sqrt(2.0 * jonswap_h(o, w) * o->dw[i] / eta);
       const double gx = 4.0 * Ly * dt * w * w * w / (M_PI * M_PI * M_PI * g);
       const double gy = 4.0 * Lx * dt * w * w * w / (M_PI * M_PI * M_PI * g);
-      P.Rx[i] = (uint64_t)llround(eta * gx * kTwo32);
-      P.Ry[i] = (uint64_t)llround(eta * gy * kTwo32);
+      P.Rx[i] = (uint64_t)llround(eta * gx * o->kappa[i][0] * kTwo32);
+      P.Ry[i] = (uint64_t)llround(eta * gy * o->kappa[i][1] * kTwo32);
       if (P.Rx[i] > ((uint64_t)1 << 52) || P.Ry[i] > ((uint64_t)1 << 52))
         return o->fail(HWO_EINVAL, "injection rate too high");
       const int64_t binu = (int64_t)o->bin_cells[i] * P.dxu;

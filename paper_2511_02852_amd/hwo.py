@@ -39,7 +39,8 @@ class HwoSpectrum(C.Structure):
                 ("wind_dir", C.c_double), ("n_buckets", C.c_int32), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("eta", C.c_double), ("max_level", C.c_int32),
                 ("subdiv_frac", C.c_double), ("h0_mode", C.c_int32),
-                ("bucket_mode", C.c_int32), ("dir_mode", C.c_int32)]
+                ("bucket_mode", C.c_int32), ("dir_mode", C.c_int32),
+                ("flux_mode", C.c_int32)]
 
 
 class HwoPatch(C.Structure):
@@ -165,7 +166,7 @@ class Ocean:
         sp = scene.spectrum
         hs = HwoSpectrum(sp.U10, sp.fetch, sp.gamma, sp.spread_s, sp.wind_dir, sp.n_buckets, sp.lambda_min,
                          sp.lambda_max, sp.eta, sp.max_level, sp.subdiv_frac, sp.h0_mode,
-                         sp.bucket_mode, sp.dir_mode)
+                         sp.bucket_mode, sp.dir_mode, sp.flux_mode)
         self._check(self.L.hwo_set_spectrum(self.h, C.byref(hs)))
         self.nb = sp.n_buckets
         pid = C.c_int32()

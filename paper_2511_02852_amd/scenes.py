@@ -43,6 +43,9 @@ class Spectrum:
       1 equal-energy buckets over [0.5 w_p, 2.5 w_p] (the lambda range is unused).
     dir_mode: 0 directions by inverse CDF of Dir, equal amplitudes; 1 stratified
       groups of eta (= N_theta, a whole number) directions, amplitude from S(w, theta).
+    flux_mode: 0 each side pair injects the group count of Eq 18; 1 obliquity-weighted:
+      the count is scaled by the mean |cos| of the crossing angle and directions are
+      drawn from Dir |cos| (needs dir_mode 0).
     """
     U10: float = 10.0
     fetch: float = 100e3
@@ -58,6 +61,7 @@ class Spectrum:
     h0_mode: int = 0
     bucket_mode: int = 0
     dir_mode: int = 0
+    flux_mode: int = 0
 
 
 @dataclass

@@ -192,6 +192,25 @@ def test_stratified_directions(name, steps, form):
     say(f"stratified {name} {form} err={e}")
 
 
+@pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "plain"),
+                                             ("c2", 60, "batched"), ("p0", 40, "batched")])
+def test_obliquity_weighted_injection(name, steps, form):
+    """Obliquity-weighted boundary injection (per side pair direction tables
+    and counts scaled by the mean crossing |cos|): integer state bit-exact and
+    heights."""
+    import dataclasses
+    s = scenes.get(name)
+    s = s.replace(spectrum=dataclasses.replace(s.spectrum, flux_mode=1, wind_dir=0.4))
+    kw = dict(compact=True, batched=True) if form == "batched" else {}
+    say(f"obliquity {name} {form} {steps} steps")
+    g, o = make(s, **kw)
+    g.step(steps)
+    o.step(steps)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s)
+    say(f"obliquity {name} {form} err={e}")
+
+
 def test_c4_far_anchor():
     s = scenes.c4()
     g, o = make(s)
