@@ -6,7 +6,7 @@
  *   (a) the FFT background: directional JONSWAP spectrum (Sec 3.1, Eq 1-6),
  *       evolved under deep-water dispersion and inverse-transformed (Sec 4.1);
  *   (b) boundary injection of wave particles into every patch, per frequency
- *       bucket, with counts from Eq "result_2" and directions drawn from the
+ *       bucket, with counts from Eq 18 and directions drawn from the
  *       same directional spectrum (Sec 3.3, Sec 4.2);
  *   (c) propagation at each bucket's phase speed c_i = g / w_i (Sec 3.2),
  *       ring emission from moving sources into the closest-radius bucket

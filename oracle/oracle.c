@@ -11,11 +11,14 @@
  *   - FFT background: Sec 3.1 (Eq 1-6) spectrum, evolved as a standard
  *     Tessendorf-style spectral field under deep-water dispersion w^2 = g k
  *     (Sec 4.1 "FFT updates"), inverse-transformed with a radix-2 FFT.
- *   - Wave-particle patches: frequency buckets (Sec 3.3, Sec 4.2) with
+ *   - Wave-particle patches: frequency buckets (log-spaced, or the
+ *     equal-energy partition of [0.5 w_p, 2.5 w_p] of Sec 3.3) with
  *     w_i, r_i = pi g / w_i^2, c_i = g / w_i (Sec 3.2 kinematics), amplitude
- *     A = sqrt(2 S dw dtheta) (Eq "A", importance-sampled form), boundary
- *     injection rate N_i = 4 L dt w_i^3 / (pi^3 g) per pair of opposite sides
- *     (Eq "result_2"), directions drawn from the directional spectrum (Sec 4.2),
+ *     A = sqrt(2 S dw dtheta) (Eq 7, importance-sampled or per stratified
+ *     direction), boundary injection rate N_i = 4 L dt w_i^3 / (pi^3 g) per
+ *     pair of opposite sides (Eq 18, optionally scaled by the mean obliquity),
+ *     directions drawn from the directional spectrum (Sec 4.2) or stratified
+ *     over N_theta sectors (Sec 3.3),
  *     fixed-point analytic propagation at c_i, ring emission from moving
  *     sources into the closest-radius bucket (Sec 4.3), 3-way subdivision,
  *     and a separable raised-cosine crest/trough pair splat (Fig 1, Sec 4.2).
@@ -28,7 +31,9 @@
  * normalisation and special case, naive DFT / numpy FFT / Parseval, single
  * mode phase speed, numpy Philox4x64, energy identity of the injection rate,
  * pair-lattice cosine sum, crest volume, subdivision conservation, blend
- * limits.  Full-scene particle bookkeeping beyond these is parity unpinned
+ * limits, equal-energy bucket integrals, stratified sector balance and the
+ * direction amplitude factor's normalisation, the steady-state spectral
+ * density of obliquity-weighted injection.  Full-scene particle bookkeeping beyond these is parity unpinned
  * except through the identities tested there.
  */
 #include "oracle.h"
@@ -424,9 +429,9 @@ int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, do
     double Lx = (double)nx * dx, Ly = (double)ny * dx;
     for (int i = 0; i < o->nb; ++i) {
         double w = o->w[i];
-        /* Eq "A", importance-sampled: A^2 = 2 S_J(w_i) dw_i / eta */
+        /* Eq 7, importance-sampled: A^2 = 2 S_J(w_i) dw_i / eta */
         p->A[i] = sqrt(2.0 * orc_jonswap(o, w) * o->dw[i] / p->eta);
-        /* Eq "result_2": groups per step for the pair of sides of length L */
+        /* Eq 18: groups per step for the pair of sides of length L */
         double gx = 4.0 * Ly * o->dt * w * w * w / (M_PI * M_PI * M_PI * o->g);
         double gy = 4.0 * Lx * o->dt * w * w * w / (M_PI * M_PI * M_PI * o->g);
         p->Rx[i] = (uint64_t)llround(p->eta * gx * o->kappa[i][0] * TWO32);
@@ -651,7 +656,7 @@ static int step_once(orc_ocean *o) {
         }
     }
 
-    /* boundary injection, Eq "result_2" per pair of opposite sides */
+    /* boundary injection, Eq 18 per pair of opposite sides */
     for (int p = 0; p < o->np; ++p) {
         patch_t *pt = &o->pt[p];
         for (int i = 0; i < o->nb; ++i) {
@@ -979,7 +984,7 @@ static double amplitude(const orc_ocean *o, const prt_t *q) {
     if (q->kind == 0) {
         const patch_t *pt = &o->pt[q->patch];
         if (o->dir_mode == 0) return pt->A[q->bucket];
-        /* Eq "A" with the particle's own direction and dtheta = 2 pi / N_theta:
+        /* Eq 7 with the particle's own direction and dtheta = 2 pi / N_theta:
          * A^2 = 2 S_J(w_i) Dir(theta) dw_i dtheta = A_{p,i}^2 * 2 pi Dir(theta) */
         double th = 2.0 * M_PI * (double)q->code / (double)NCODE - o->wind_dir;
         return pt->A[q->bucket] * sqrt(2.0 * M_PI * dir_s(orc_spread(o, o->w[q->bucket]), th));

@@ -5,7 +5,7 @@
 //              patches that follow a source (FP64 source position), compute
 //              the FP64 background offsets of every patch, the boundary
 //              injection count of every (patch, bucket, side pair) from the
-//              32.32 rate of Eq "result_2", the ring emissions of every
+//              32.32 rate of Eq 18, the ring emissions of every
 //              source (Sec 4.3), and their prefix sums.
 //   k_update   persistent grid over all work items of the step: previous
 //   <count>    particles (subdivide, then survive), new boundary particles

@@ -7,11 +7,14 @@
 //   buckets    log-spaced wavelength edges or the equal-energy partition of
 //              [0.5 w_p, 2.5 w_p], w_i = geometric mean of the edge
 //              frequencies, r_i = pi g / w_i^2, c_i = g / w_i (Sec 3.2)
-//   directions 64 bins, integer weights round(Dir dtheta 2^30), codes in units
-//              of 2 pi / 10368; CDF by a wave64 scan on the GPU
+//   directions 64 bins, integer weights round(Dir dtheta 2^30) (times the
+//              side pair's |cos| when obliquity-weighted), codes in units
+//              of 2 pi / 10368; CDF by a wave64 scan on the GPU; for
+//              stratified groups the factor sqrt(2 pi Dir) per code
 //   velocity   round(c_i dt (cos, sin) 2^32) per code, int32
-//   rates      round(eta 4 L dt w_i^3 / (pi^3 g) 2^32) per side pair (Eq "result_2")
-//   amplitude  sqrt(2 S_J(w_i) dw_i / eta) (Eq "A", importance-sampled)
+//   rates      round(eta 4 L dt w_i^3 / (pi^3 g) kappa 2^32) per side pair
+//              (Eq 18; kappa = 1, or the pair's mean obliquity)
+//   amplitude  sqrt(2 S_J(w_i) dw_i / eta) (Eq 7, importance-sampled)
 //   sources    closest-radius bucket, ring offsets / multipliers, emission
 //              cadence, crest volume = swept volume, subdivision ages
 // h0(k) and the FFT twiddles are generated on the GPU in FP64.

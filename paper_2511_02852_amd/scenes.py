@@ -243,13 +243,17 @@ def p0() -> Scene:
     """The paper's default parameters (Sec 5): U10 = 5 m/s, fetch 10 km,
     N_omega = N_theta = 16, a 100 m wave-particle region at 512^2 cells and a
     500 m FFT ocean at 512^2.  Buckets are the paper's equal-energy partition
-    of [0.5 w_p, 2.5 w_p], spreading is Mitsuyasu's s(w) and gamma follows
-    from the fetch.  The region follows a small moving source (a boat).
+    of [0.5 w_p, 2.5 w_p], spreading is Mitsuyasu's s(w), gamma follows from
+    the fetch, and each injected group holds N_theta stratified directions
+    with amplitudes from S(w, theta); the group count per side pair is the
+    paper's (no obliquity weighting).  The region follows a small moving
+    source (a boat).
     About 0.9M particles are live after the ~3600 steps that the slowest
     waves need to cross the region.  Bin edges (cells) are chosen for this
     spectrum's bucket wavelengths (about 1.8-19.7 m, i.e. 9-101 cells)."""
     sp = Spectrum(U10=5.0, fetch=10e3, gamma=0.0, spread_s=-1.0, wind_dir=0.0,
-                  n_buckets=16, lambda_min=1.0, lambda_max=2.0, eta=16.0, bucket_mode=1)
+                  n_buckets=16, lambda_min=1.0, lambda_max=2.0, eta=16.0, bucket_mode=1,
+                  dir_mode=1)
     h = math.radians(30.0)
     src = Source(x0=250.0, y0=250.0, vx=3.0 * math.cos(h), vy=3.0 * math.sin(h),
                  radius=2.5, draft=0.5, ring_n=64, patch=0)

@@ -173,7 +173,7 @@ def test_velocity_table_fixed_point():
 
 
 def test_injection_energy_identity():
-    """Eq "energy_1" = N_i x group energy (Eq "energy_2"): with importance
+    """Eq 12 = N_i x group energy (Eq 15): with importance
     sampling each of the eta particles of a group carries A^2 = 2 S_J dw / eta,
     so for a square patch N_i * eta * (1/8 rho g A^2 pi r^2) must equal
     2 rho g L dt (g / w) S_J(w) dw (the direction integral of Dir is 1)."""
@@ -193,7 +193,7 @@ def test_injection_energy_identity():
 
 
 def test_injection_rate_scales_with_w_cubed_and_side():
-    """Eq "result_2": the rate per pair is proportional to w_i^3 and to the
+    """Eq 18: the rate per pair is proportional to w_i^3 and to the
     length of the sides of that pair."""
     s = scenes.c1()
     s.patches[0].nx = 96  # rectangle 48 m x 32 m
