@@ -85,6 +85,7 @@ struct orc_ocean {
     double L, g, dt;
     uint64_t seed;
     int have_spec, stepped, bins_set;
+    int32_t synth;               /* 0 exact-position splat, 1 texel layers + separable passes */
     double U10, fetch, gamma, s_const, wind_dir, alpha, wp, eta, subdiv_frac;
     int32_t nb, lmax, h0_mode, wind_code, dir_mode, flux_mode;
     double lam_min, lam_max;
@@ -1044,6 +1045,85 @@ static void splat_particle(const orc_ocean *o, const patch_t *pt, double *raw, c
     splat_kernel(o, pt, raw, (double)px - tx, (double)py - ty, -A, r, wxv, wyv);
 }
 
+/* ---------------------------------------------------------------- texel layers
+ * Sec 4.2 synthesis: every particle point (crest +A at p, trough -A at
+ * p - r u) is accumulated into its bucket's layer texture on the patch's cell
+ * grid, each layer is smoothed by a pass along x and then along y with the
+ * raised cosine sampled at whole-cell offsets, and the layers are summed.
+ * Deposit is bilinear onto the four surrounding cell centres (the paper does
+ * not state the deposit; bilinear keeps the texel result within O(dx^2) of
+ * the exact-position kernel).  The trough offset is rounded to position
+ * units, round(r (cos, sin) 2^20), so texel choices are exact integers.
+ * A layer spans the patch plus R = ceil(r / dx) - 1 cells on each side: the
+ * taps w(k dx) are non-zero for |k| <= R only, so deposits farther out never
+ * reach a patch cell. */
+static int64_t layer_reach(const patch_t *pt, double r) {
+    int64_t R = (int64_t)ceil(r / pt->dx) - 1;
+    return R < 0 ? 0 : R;
+}
+
+static void deposit(const patch_t *pt, double *lay, int64_t R, int64_t xu, int64_t yu, double A) {
+    const int64_t W = pt->nx + 2 * R, Hh = pt->ny + 2 * R;
+    const int64_t h = pt->dxu / 2;
+    int64_t X = xu - pt->wx * pt->dxu - h, Y = yu - pt->wy * pt->dxu - h;
+    int64_t i0 = fdiv(X, pt->dxu), j0 = fdiv(Y, pt->dxu);
+    double tx = (double)(X - i0 * pt->dxu) / (double)pt->dxu;
+    double ty = (double)(Y - j0 * pt->dxu) / (double)pt->dxu;
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) {
+            int64_t i = i0 + di + R, j = j0 + dj + R;
+            if (i < 0 || i >= W || j < 0 || j >= Hh) continue;
+            double wgt = (di ? tx : 1.0 - tx) * (dj ? ty : 1.0 - ty);
+            lay[j * W + i] += A * wgt;
+        }
+}
+
+static void layer_synth(const orc_ocean *o, const patch_t *pt, double *raw, const prt_t *P, int64_t n, int32_t p) {
+    for (int b = 0; b < o->nb; ++b) {
+        const double r = o->r[b];
+        const int64_t R = layer_reach(pt, r);
+        const int64_t W = pt->nx + 2 * R, Hh = pt->ny + 2 * R;
+        double *lay = (double *)calloc((size_t)(W * Hh), sizeof(double));
+        double *T = (double *)calloc((size_t)(pt->nx * Hh), sizeof(double));
+        double *w = (double *)malloc(sizeof(double) * (size_t)(2 * R + 1));
+        for (int64_t k = -R; k <= R; ++k) w[k + R] = wker((double)k * pt->dx, r);
+        for (int64_t k = 0; k < n; ++k) {
+            const prt_t *q = &P[k];
+            if (q->patch != p || q->bucket != b) continue;
+            int64_t px, py;
+            position(o, q, o->n, &px, &py);
+            double A = amplitude(o, q);
+            double ang = 2.0 * M_PI * (double)q->code / (double)NCODE;
+            int64_t tx = llround(r * cos(ang) * UNIT), ty = llround(r * sin(ang) * UNIT);
+            deposit(pt, lay, R, px, py, A);
+            deposit(pt, lay, R, px - tx, py - ty, -A);
+        }
+        /* pass along x: T[j][i] = sum_k lay[j][i + R - k] w(k dx), i in the patch */
+        for (int64_t j = 0; j < Hh; ++j)
+            for (int64_t i = 0; i < pt->nx; ++i) {
+                double s = 0.0;
+                for (int64_t k = -R; k <= R; ++k) s += lay[j * W + i + R - k] * w[k + R];
+                T[j * pt->nx + i] = s;
+            }
+        /* pass along y, summed into the patch map */
+        for (int64_t j = 0; j < pt->ny; ++j)
+            for (int64_t i = 0; i < pt->nx; ++i) {
+                double s = 0.0;
+                for (int64_t k = -R; k <= R; ++k) s += T[(j + R - k) * pt->nx + i] * w[k + R];
+                raw[j * pt->nx + i] += s;
+            }
+        free(lay);
+        free(T);
+        free(w);
+    }
+}
+
+int orc_set_synthesis(orc_ocean *o, int32_t mode) {
+    if (mode != 0 && mode != 1) return fail(o, "synthesis mode must be 0 or 1");
+    o->synth = mode;
+    return 0;
+}
+
 static void blend(const orc_ocean *o, const patch_t *pt, const double *H, const double *raw,
                   double *out) {
     int32_t N = o->N;
@@ -1077,13 +1157,17 @@ int orc_patch_maps(orc_ocean *o, int32_t p, const double *H, double *raw, double
     const patch_t *pt = &o->pt[p];
     size_t nc = (size_t)pt->nx * pt->ny;
     memset(raw, 0, sizeof(double) * nc);
-    int64_t wmax = pt->nx > pt->ny ? pt->nx : pt->ny;
-    double *wxv = (double *)malloc(sizeof(double) * (size_t)(wmax + 8));
-    double *wyv = (double *)malloc(sizeof(double) * (size_t)(wmax + 8));
-    for (int64_t k = 0; k < o->nP; ++k)
-        if (o->P[k].patch == p) splat_particle(o, pt, raw, &o->P[k], wxv, wyv);
-    free(wxv);
-    free(wyv);
+    if (o->synth == 1) {
+        layer_synth(o, pt, raw, o->P, o->nP, p);
+    } else {
+        int64_t wmax = pt->nx > pt->ny ? pt->nx : pt->ny;
+        double *wxv = (double *)malloc(sizeof(double) * (size_t)(wmax + 8));
+        double *wyv = (double *)malloc(sizeof(double) * (size_t)(wmax + 8));
+        for (int64_t k = 0; k < o->nP; ++k)
+            if (o->P[k].patch == p) splat_particle(o, pt, raw, &o->P[k], wxv, wyv);
+        free(wxv);
+        free(wyv);
+    }
     if (blended) {
         double *Hown = NULL;
         if (!H) {
@@ -1129,6 +1213,8 @@ int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *r
     int64_t wmax = pt->nx > pt->ny ? pt->nx : pt->ny;
     double *wxv = (double *)malloc(sizeof(double) * (size_t)(wmax + 8));
     double *wyv = (double *)malloc(sizeof(double) * (size_t)(wmax + 8));
+    prt_t *keep = (prt_t *)malloc(sizeof(prt_t) * (size_t)(n > 0 ? n : 1));
+    int64_t nk = 0;
     for (int64_t k = 0; k < n; ++k) {
         const int64_t *d = recs + 10 * k;
         prt_t q;
@@ -1144,8 +1230,11 @@ int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *r
         q.slot = (int32_t)d[9];
         if (q.patch != p || q.bucket < 0 || q.bucket >= o->nb || q.code < 0 || q.code >= NCODE) continue;
         if (q.kind == 1 && (q.src < 0 || q.src >= o->ns)) continue;
-        splat_particle(o, pt, raw, &q, wxv, wyv);
+        if (o->synth == 1) keep[nk++] = q;
+        else splat_particle(o, pt, raw, &q, wxv, wyv);
     }
+    if (o->synth == 1) layer_synth(o, pt, raw, keep, nk, p);
+    free(keep);
     free(wxv);
     free(wyv);
     return 0;

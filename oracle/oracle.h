@@ -37,6 +37,9 @@ int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, do
 int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,
                    double draft, int32_t ring_n, int32_t patch);
 int orc_set_bins(orc_ocean *o, const int32_t *bin_cells);
+/* Height synthesis: 0 the exact-position separable splat, 1 texel layers per
+ * bucket (bilinear deposit) smoothed by separable x and y passes (Sec 4.2). */
+int orc_set_synthesis(orc_ocean *o, int32_t mode);
 int orc_step(orc_ocean *o, int32_t nsteps);
 int64_t orc_step_index(const orc_ocean *o);
 

@@ -118,6 +118,8 @@ class Scene:
     # record form and launch form
     compact: bool = False
     batched: bool = False
+    # height synthesis: 0 exact-position splat, 1 texel layers + separable passes
+    synth: int = 0
 
     def replace(self, **kw) -> "Scene":
         return dataclasses.replace(self, **kw)

@@ -507,3 +507,72 @@ def test_flux_mode_validation():
         bad = s.replace(spectrum=dataclasses.replace(s.spectrum, **kw))
         with pytest.raises(oracle.OracleError):
             oracle.Oracle(bad)
+
+
+# ---------------------------------------------------------------- texel-layer synthesis
+def texel_pair(s, synth, x_u, y_u, code, bucket=0):
+    o = oracle.Oracle(s.replace(synth=synth))
+    return o.splat(0, np.array([rec(x_u, y_u, code, bucket=bucket)]))
+
+
+def test_texel_layers_equal_exact_splat_at_cell_centres():
+    """Sec 4.2 synthesis (deposit into a bucket layer, then a pass along x and
+    one along y): a crest and trough sitting on cell centres deposit into one
+    texel each, and the separable passes then evaluate the raised cosine at
+    exact cell offsets, so the layer map equals the exact-position splat."""
+    s = pin_scene()
+    dxu = int(s.patches[0].dx * UNIT)
+    for code in (0, oracle.NCODE // 4, oracle.NCODE // 2):
+        for (i, j) in ((20, 31), (1, 2), (63, 0)):
+            xu, yu = i * dxu + dxu // 2, j * dxu + dxu // 2
+            h0 = texel_pair(s, 0, xu, yu, code)
+            h1 = texel_pair(s, 1, xu, yu, code)
+            assert np.max(np.abs(h0)) > 0.1 * o_amp(s)
+            assert np.max(np.abs(h1 - h0)) <= 1e-12 * o_amp(s)
+
+
+def o_amp(s):
+    return oracle.Oracle(s).patch_bucket(0, 0)["A"]
+
+
+def test_texel_layers_second_order_in_cell_size():
+    """Bilinear deposit makes the layer map the bilinear interpolant, in the
+    particle position, of the exact kernel: per point the error is at most
+    A dx^2 max|w''| / 4 = A dx^2 pi^2 / (8 r^2), and it falls by 4 when dx
+    halves.  Particles up to a radius outside the patch count too."""
+    rng = np.random.default_rng(7)
+    errs = []
+    for nx, dx in ((64, 0.25), (128, 0.125)):
+        s = pin_scene(nx=nx, dx=dx)
+        A = o_amp(s)
+        r = 1.0
+        bound = 2 * A * dx * dx * math.pi ** 2 / (8 * r * r)
+        L = nx * dx
+        worst = 0.0
+        for _ in range(12):
+            x, y = rng.uniform(-r, L + r, size=2)
+            code = int(rng.integers(0, oracle.NCODE))
+            xu, yu = int(round(x * UNIT)), int(round(y * UNIT))
+            d = np.max(np.abs(texel_pair(s, 1, xu, yu, code) - texel_pair(s, 0, xu, yu, code)))
+            assert d <= bound * (1 + 1e-9), (nx, x, y, code, d, bound)
+            worst = max(worst, d / A)
+        errs.append(worst)
+    assert errs[0] / errs[1] > 3.0
+
+
+def test_texel_layers_sum_buckets_and_blend():
+    """Layers are summed: a scene's texel map is the sum of its particles'
+    maps; the mode changes the splat only (same particles, same blend)."""
+    s = scenes.c1().replace(synth=1)
+    o = oracle.Oracle(s)
+    o.step(6)
+    P = o.particles()
+    raw, bl = o.patch_maps(0)
+    parts = sum(o.splat(0, P[P[:, 1] == b]) for b in range(o.nb))
+    assert np.max(np.abs(raw - parts)) <= 1e-12 * max(np.max(np.abs(raw)), 1.0)
+    s0 = scenes.c1()
+    o0 = oracle.Oracle(s0)
+    o0.step(6)
+    assert np.array_equal(o0.particles(), P)
+    raw0, _ = o0.patch_maps(0)
+    assert np.sqrt(np.mean((raw - raw0) ** 2)) < 0.05 * np.sqrt(np.mean(raw0 ** 2))
