@@ -68,6 +68,11 @@ typedef struct {
     hwo_free_fn dev_free;
     void *alloc_ctx;
     int64_t max_particles;  /* particle capacity; 0 selects an estimate */
+    int32_t synth;          /* height synthesis: 0 the separable kernel at each
+                               particle's exact position (default); 1 the paper's
+                               texel layers (Sec 4.2) -- bilinear deposit per bucket,
+                               passes along x and y with the raised cosine at
+                               whole-cell offsets, layers summed */
 } hwo_config;
 
 /* Spectrum and bucket parameters (Sec 3.1, Sec 3.3). */
@@ -168,7 +173,8 @@ int hwo_read_tiles(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dst, in
 int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_out);
 
 /* Test hook: splat caller-placed canonical records into patch p's raw map at
- * the current step (no binning), result in dst (host, ny x nx). */
+ * the current step (no binning), result in dst (host, ny x nx).  With synth 1
+ * the records go through the texel layers instead (which it overwrites). */
 int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, float *dst,
                    int64_t dst_elems);
 
@@ -176,18 +182,22 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * launch with HIP events (graph replay is then disabled); hwo_stage_times
  * returns accumulated milliseconds and launch counts per stage:
  *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat
- *   7 splat_plan  8 splat_reduce  9 bin_plan (n >= 10).  bin_plan is the
- *   one-block scan + tile estimates + plan that replaces stages 4 and 7 in
- *   the batched form of scenes with at most 65536 bins and 4096 tiles. */
+ *   7 splat_plan  8 splat_reduce  9 bin_plan  10 layer_clear  11 deposit
+ *   12 filter_x  13 filter_y (n >= 14).  bin_plan is the one-block scan +
+ *   tile estimates + plan that replaces stages 4 and 7 in the batched form of
+ *   scenes with at most 65536 bins and 4096 tiles.  Stages 6-8 run with
+ *   synth 0, stages 10-13 with synth 1. */
 int hwo_set_timing(hwo_ocean *o, int32_t enable);
 int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
 /* Benchmark support: after at least one step, launch the kernels of one
  * stage reps times back to back between two HIP events on the library stream
  * and store the mean milliseconds per repetition (all launch groups of the
  * stage).  Only stages whose kernels are idempotent for a finished frame are
- * accepted: 1 fft_a, 2 fft_b, 6 splat, 7 splat_plan, 8 splat_reduce; any other
- * stage gives HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are
- * rewritten with the same values (up to FP32 summation order). */
+ * accepted: 1 fft_a, 2 fft_b, 6 splat, 7 splat_plan, 8 splat_reduce (synth 0),
+ * 10 layer_clear, 12 filter_x, 13 filter_y (synth 1); any other stage gives
+ * HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are rewritten
+ * with the same values (up to FP32 summation order), except that layer_clear
+ * leaves the layers empty until the next step. */
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep);
 /* Bytes of particle storage per record for the active form (16 or 32). */
 int32_t hwo_record_bytes(const hwo_ocean *o);

@@ -86,6 +86,10 @@ struct PatchDev {
   uint64_t Rx[kMaxBuckets], Ry[kMaxBuckets];
   int32_t binu[kMaxBuckets];   // bin edge (position units)
   int32_t nbx[kMaxBuckets], nby[kMaxBuckets], binbase[kMaxBuckets];
+  // texel-layer synthesis: per bucket, the layer (patch plus lay_R cells on
+  // every side, row-major) and its x-filtered copy (patch columns only)
+  int64_t lay_off[kMaxBuckets], lt_off[kMaxBuckets];
+  int32_t lay_R[kMaxBuckets], tap_off[kMaxBuckets];
 };
 
 struct SourceDev {
@@ -162,6 +166,16 @@ struct Dev {
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
   int32_t max_items;           // capacity of partials (items)
   uint32_t chunk_load;         // least estimated cost of a work item
+  // texel-layer synthesis (synth == 1)
+  int32_t synth;
+  int32_t nlayer_rows;         // rows of all layers
+  int64_t lay_n;               // floats in all layers (multiple of 4)
+  float *lay;                  // layers, all patches and buckets
+  float *lt;                   // x-filtered layers
+  const float *taps;           // raised cosine at whole-cell offsets, 2R+1 per (patch, bucket)
+  const int32_t *row_base;     // [np * nb + 1] first layer row of each (patch, bucket)
+  const int2 *toff;            // [nb][kNCode] trough offset round(r (cos, sin) 2^20)
+  int32_t xsmem, ysmem;        // dynamic LDS bytes of the two passes
 };
 
 // ---------------------------------------------------------------- helpers
@@ -252,6 +266,63 @@ __device__ inline float particle_amp(const Dev &d, const Part &p) {
   return s.B * d.ring_m[s.ring0 + m_slot(m)] * inv3[m_level(m)];
 }
 
+// ---------------------------------------------------------------- output tiles
+// Patch maps are cut into kTile x kTile output tiles, numbered patch by patch.
+struct TileGeom {
+  int p, i0, j0, tw, th;
+  float Ab;            // boundary amplitude of the bucket being splatted
+  int64_t X0, Y0;      // first cell centre (position units)
+  float inv_dxu;
+};
+
+__device__ __forceinline__ int patch_of_tile(const Dev &d, int tile) {
+  int lo = 0, hi = d.np - 1;   // last patch with tile0 <= tile
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d.patches[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void tile_geom(const Dev &d, int tile, int p, TileGeom &T) {
+  const PatchDev &P = d.patches[p];
+  const StepPatch &W = d.sp[p];
+  T.p = p;
+  const int lt = tile - P.tile0;
+  T.i0 = (lt % P.ntx) * kTile;
+  T.j0 = (lt / P.ntx) * kTile;
+  T.tw = min(kTile, P.nx - T.i0);
+  T.th = min(kTile, P.ny - T.j0);
+  T.X0 = ((int64_t)W.wx + T.i0) * P.dxu + P.dxu / 2;
+  T.Y0 = ((int64_t)W.wy + T.j0) * P.dxu + P.dxu / 2;
+  T.inv_dxu = 1.0f / (float)P.dxu;
+}
+
+// Blend one cell (tile-local i, j) and store the raw and blended heights.
+__device__ __forceinline__ void blend_store(const Dev &d, const PatchDev &P, const StepPatch &W, const TileGeom &T,
+                                            int i, int j, float h, float *__restrict__ raw_out,
+                                            float *__restrict__ blend_out, int64_t out_off) {
+  const int ci = T.i0 + i, cj = T.j0 + j;
+  const size_t o = (size_t)(P.cell0 - out_off) + (size_t)cj * P.nx + ci;
+  raw_out[o] = h;
+  if (!blend_out) return;
+  const int N = d.N;
+  const float dx = (float)P.dx;
+  const float dd = fminf(fminf((float)ci + 0.5f, (float)P.nx - (float)ci - 0.5f),
+                         fminf((float)cj + 0.5f, (float)P.ny - (float)cj - 0.5f)) * dx;
+  const float t = fminf(dd * P.inv_band, 1.f);
+  const float s = t * t * (3.f - 2.f * t);
+  const float uu = W.fx0 + (float)ci * P.ratio, vv = W.fy0 + (float)cj * P.ratio;
+  const float fu = floorf(uu), fv = floorf(vv);
+  const float a = uu - fu, bb = vv - fv;
+  const int x0 = (W.gx0 + (int)fu) & (N - 1), y0 = (W.gy0 + (int)fv) & (N - 1);
+  const int x1 = (x0 + 1) & (N - 1), y1 = (y0 + 1) & (N - 1);
+  const float *Hr0 = d.H + (size_t)y0 * N, *Hr1 = d.H + (size_t)y1 * N;
+  const float hb = (1.f - bb) * ((1.f - a) * Hr0[x0] + a * Hr0[x1]) + bb * ((1.f - a) * Hr1[x0] + a * Hr1[x1]);
+  blend_out[o] = s * h + (1.f - s) * hb;
+}
+
+
 // ---------------------------------------------------------------- launchers
 void launch_h0(const Dev &d, float2 *h0T, float2 *tw, double alpha, double wp, double gamma,
                double s_const, double wind_dir, int h0_mode, hipStream_t st);
@@ -269,6 +340,12 @@ void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st);
 void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw,
                          int64_t out_off, hipStream_t st);
 void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, hipStream_t st);
+// Texel-layer synthesis.
+hipError_t prepare_layers(const Dev &d);
+void launch_layer_clear(const Dev &d, hipStream_t st);
+void launch_deposit(const Dev &d, const void *recs, int n, hipStream_t st);
+void launch_filter_x(const Dev &d, hipStream_t st);
+void launch_filter_y(const Dev &d, int t0, int ntiles, float *raw, float *blend, int64_t out_off, hipStream_t st);
 int scan_blocks(int nbins);
 
 }  // namespace hwo

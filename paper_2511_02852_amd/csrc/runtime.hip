@@ -37,8 +37,9 @@ namespace {
 constexpr double kUnit = 1048576.0;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kTwo30 = 1073741824.0;
-constexpr int kStages = 10;
-enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE, ST_BINPLAN };
+constexpr int kStages = 14;
+enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE, ST_BINPLAN,
+       ST_LCLEAR, ST_DEPOSIT, ST_FILTX, ST_FILTY };
 
 int64_t pmod(int64_t a, int64_t m) {
   int64_t r = a % m;
@@ -74,6 +75,12 @@ struct hwo_ocean {
   std::vector<int32_t> codes;      // [64]
   int32_t wind_code = 0;           // wind direction in direction-code units
   std::vector<float> afac;         // [nb][kNCode] sqrt(2 pi Dir); stratified directions only
+  // texel-layer synthesis tables
+  std::vector<float> taps;         // 2R+1 raised-cosine taps per (patch, bucket)
+  std::vector<int32_t> row_base;   // first layer row per (patch, bucket), np*nb+1
+  std::vector<int2> toff;          // [nb][kNCode] trough offsets (units)
+  int64_t lay_total = 0, lt_total = 0;
+  int32_t max_R = 0, max_nx = 0;
   std::vector<int2> V;             // [nb][kNCode]
   std::vector<float2> UC;          // [kNCode]
   // scene tables
@@ -202,6 +209,7 @@ int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out) {
   if (N < 16 || N > 4096 || (N & (N - 1)) != 0) return HWO_EINVAL;
   if (!(cfg->fft_L > 0) || !(cfg->g > 0) || !(cfg->dt > 0)) return HWO_EINVAL;
   if (cfg->max_particles < 0 || cfg->max_particles > ((int64_t)1 << 30)) return HWO_EINVAL;
+  if (cfg->synth != 0 && cfg->synth != 1) return HWO_EINVAL;
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return HWO_EINVAL;
   hwo_ocean *o = new hwo_ocean();
   o->cfg = *cfg;
@@ -430,6 +438,13 @@ static int build_scene_tables(hwo_ocean *o) {
                    [&](int a, int b) { return o->sources[a].patch < o->sources[b].patch; });
   o->pdev.assign(np, PatchDev{});
   int64_t bins = 0, tiles = 0, cells = 0;
+  const bool layers = o->cfg.synth == 1;
+  o->taps.clear();
+  o->row_base.clear();
+  o->lay_total = o->lt_total = 0;
+  o->max_R = 0;
+  o->max_nx = 0;
+  int64_t rows = 0;
   const double dxf = o->cfg.fft_L / (double)o->cfg.fft_n;
   for (int p = 0; p < np; ++p) {
     const hwo_patch &hp = o->patches[p];
@@ -473,7 +488,28 @@ static int build_scene_tables(hwo_ocean *o) {
       if ((63 * (int64_t)P.dxu + 2 * m) / binu + 2 > 32)
         return o->fail(HWO_EINVAL, "bin edge too small for the bucket radius (a tile would need > 32 bin rows)");
       if (bins > ((int64_t)1 << 28)) return o->fail(HWO_EINVAL, "too many bins");
+      if (layers) {
+        // layer = patch + R cells each side, R = ceil(r / dx) - 1 (taps w(k dx) > 0 for |k| <= R)
+        const int64_t Rl = std::max<int64_t>(0, (int64_t)ceil(o->r[i] / hp.dx) - 1);
+        if (Rl > 2048) return o->fail(HWO_EINVAL, "bucket radius too large for texel layers");
+        P.lay_R[i] = (int32_t)Rl;
+        P.lay_off[i] = o->lay_total;
+        P.lt_off[i] = o->lt_total;
+        P.tap_off[i] = (int32_t)o->taps.size();
+        o->lay_total += ((int64_t)hp.nx + 2 * Rl) * ((int64_t)hp.ny + 2 * Rl);
+        o->lt_total += (int64_t)hp.nx * ((int64_t)hp.ny + 2 * Rl);
+        for (int64_t k = -Rl; k <= Rl; ++k) {
+          const double dk = (double)k * hp.dx;
+          o->taps.push_back((float)(fabs(dk) >= o->r[i] ? 0.0 : 0.5 * (1.0 + cos(M_PI * dk / o->r[i]))));
+        }
+        o->row_base.push_back((int32_t)rows);
+        rows += (int64_t)hp.ny + 2 * Rl;
+        o->max_R = std::max(o->max_R, (int32_t)Rl);
+        if (rows > ((int64_t)1 << 30) || o->lay_total > ((int64_t)1 << 34))
+          return o->fail(HWO_EINVAL, "texel layers too large");
+      }
     }
+    o->max_nx = std::max(o->max_nx, (int32_t)hp.nx);
     P.bin_hi = (int32_t)bins;
     P.ntx = (hp.nx + kTile - 1) / kTile;
     P.nty = (hp.ny + kTile - 1) / kTile;
@@ -483,6 +519,7 @@ static int build_scene_tables(hwo_ocean *o) {
     P.cell0 = cells;
     cells += (int64_t)hp.nx * hp.ny;
   }
+  if (layers) o->row_base.push_back((int32_t)rows);
   // source ranges per patch in sorted order
   for (int p = 0; p < np; ++p) {
     int lo = 0;
@@ -691,6 +728,34 @@ static int finalize(hwo_ocean *o) {
   }
   if (!d.item_desc) return o->fail(HWO_ENOMEM, "device allocation failed");
   d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
+  d.synth = o->cfg.synth;
+  if (d.synth == 1 && np > 0) {
+    d.nlayer_rows = o->row_base.back();
+    // trough offsets round(r (cos, sin) 2^20): the texel a trough lands in is an integer decision
+    o->toff.resize((size_t)nb * kNCode);
+    for (int b = 0; b < nb; ++b)
+      for (int code = 0; code < kNCode; ++code) {
+        const double ang = 2.0 * M_PI * (double)code / (double)kNCode;
+        o->toff[(size_t)b * kNCode + code] =
+            make_int2((int32_t)llround(o->r[b] * cos(ang) * kUnit), (int32_t)llround(o->r[b] * sin(ang) * kUnit));
+      }
+    d.lay_n = (o->lay_total + 3) & ~(int64_t)3;
+    d.lay = (float *)o->alloc(sizeof(float) * (size_t)d.lay_n);
+    d.lt = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(o->lt_total, 1));
+    d.taps = upload(o, o->taps, &rc);
+    d.row_base = upload(o, o->row_base, &rc);
+    d.toff = upload(o, o->toff, &rc);
+    if (rc) return rc;
+    if (!d.lay || !d.lt) return o->fail(HWO_ENOMEM, "device allocation failed");
+    const int64_t xs = sizeof(float) * ((int64_t)o->max_nx + 2 * o->max_R + 2 * o->max_R + 1);
+    const int64_t ys = sizeof(float) * (((int64_t)kTile + 2 * o->max_R) * kTile + 2 * o->max_R + 1);
+    if (xs > 160 * 1024 || ys > 160 * 1024) return o->fail(HWO_EINVAL, "texel-layer filter does not fit in LDS");
+    d.xsmem = (int32_t)xs;
+    d.ysmem = (int32_t)ys;
+    HWO_CHECK(prepare_layers(d));
+    HWO_CHECK(hipMemsetAsync(d.lay, 0, sizeof(float) * (size_t)d.lay_n, o->st));
+    HWO_CHECK(hipMemsetAsync(d.lt, 0, sizeof(float) * (size_t)std::max<int64_t>(o->lt_total, 1), o->st));
+  }
   if (!d.tile_load || !d.tile_meas || !d.tile_model || !d.tile_ratio || !d.item_base || !d.splat_ctl ||
       !d.split_tiles || !d.partials)
     return o->fail(HWO_ENOMEM, "device allocation failed");
@@ -751,6 +816,10 @@ static void launch_stage(hwo_ocean *o, int stage, const PatchArg *g) {
       break;
     case ST_REDUCE: launch_splat_reduce(d, g->t0, g->t1 - g->t0, o->st); break;
     case ST_BINPLAN: launch_bin_plan(d, d.nbins, d.ntiles, o->items_target, o->st); break;
+    case ST_LCLEAR: launch_layer_clear(d, o->st); break;
+    case ST_DEPOSIT: launch_deposit(d, nullptr, 0, o->st); break;
+    case ST_FILTX: launch_filter_x(d, o->st); break;
+    case ST_FILTY: launch_filter_y(d, 0, d.ntiles, d.raw, d.blend, 0, o->st); break;
     default: break;
   }
 }
@@ -814,20 +883,32 @@ static void run_step(hwo_ocean *o) {
   };
   if (o->dev.np > 0) {
     const std::vector<PatchArg> groups = launch_groups(o);
+    const bool layers = o->dev.synth == 1;
     if (o->fused) {
       // one group: the plan needs only the bin offsets, so it precedes the scatter
       timed(o, ST_COUNT, &groups[0]);
       timed(o, ST_BINPLAN, &groups[0]);
       timed(o, ST_SCATTER, &groups[0]);
-      join();
-      timed(o, ST_SPLAT, &groups[0]);
-      timed(o, ST_REDUCE, &groups[0]);
     } else {
       for (const auto &gp : groups) {
         timed(o, ST_COUNT, &gp);
         timed(o, ST_SCAN, &gp);
         timed(o, ST_SCATTER, &gp);
       }
+    }
+    if (layers) {
+      // texel layers of all patches: deposit, pass along x, then (with the
+      // background) pass along y, layer sum and blend
+      timed(o, ST_LCLEAR, nullptr);
+      timed(o, ST_DEPOSIT, nullptr);
+      timed(o, ST_FILTX, nullptr);
+      join();
+      timed(o, ST_FILTY, nullptr);
+    } else if (o->fused) {
+      join();
+      timed(o, ST_SPLAT, &groups[0]);
+      timed(o, ST_REDUCE, &groups[0]);
+    } else {
       for (const auto &gp : groups) {
         timed(o, ST_PLAN, &gp);
         join();
@@ -1069,7 +1150,7 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
       r.ox = (int32_t)q[6]; r.oy = (int32_t)q[7]; r.birth = (int32_t)q[5]; r.code = (int32_t)q[4];
       r.meta = meta;
       float amp;
-      if (q[2] == 0) amp = P.A[q[1]];
+      if (q[2] == 0) amp = P.A[q[1]] * (o->afac.empty() ? 1.f : o->afac[(size_t)q[1] * kNCode + q[4]]);
       else {
         const SourceDev &S = o->sdev[q[8]];
         amp = S.B * o->ring_m[S.ring0 + q[9]];
@@ -1085,7 +1166,14 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
   HWO_CHECK(hipMalloc((void **)&dout, sizeof(float) * (size_t)cells));
   hipError_t e = hipMemcpyAsync(drec, host.data(), host.size(), hipMemcpyHostToDevice, o->st);
   if (e == hipSuccess) {
-    launch_splat_direct(d, P.tile0, P.ntx * P.nty, drec, (int)n, dout, P.cell0, o->st);
+    if (d.synth == 1) {
+      launch_layer_clear(d, o->st);
+      launch_deposit(d, drec, (int)n, o->st);
+      launch_filter_x(d, o->st);
+      launch_filter_y(d, P.tile0, P.ntx * P.nty, dout, nullptr, P.cell0, o->st);
+    } else {
+      launch_splat_direct(d, P.tile0, P.ntx * P.nty, drec, (int)n, dout, P.cell0, o->st);
+    }
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipMemcpyAsync(dst, dout, sizeof(float) * (size_t)cells, hipMemcpyDeviceToHost, o->st);
@@ -1121,8 +1209,12 @@ int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n) {
 
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep) {
   if (!o || !ms_per_rep || reps < 1) return HWO_EINVAL;
-  if (stage != ST_FFT_A && stage != ST_FFT_B && stage != ST_PLAN && stage != ST_SPLAT && stage != ST_REDUCE)
+  const bool splat_stage = stage == ST_PLAN || stage == ST_SPLAT || stage == ST_REDUCE;
+  const bool layer_stage = stage == ST_LCLEAR || stage == ST_FILTX || stage == ST_FILTY;
+  if (stage != ST_FFT_A && stage != ST_FFT_B && !splat_stage && !layer_stage)
     return o->fail(HWO_EINVAL, "stage is not repeatable (it advances or consumes state)");
+  if ((splat_stage && o->cfg.synth == 1) || (layer_stage && o->cfg.synth != 1))
+    return o->fail(HWO_EINVAL, "stage is not part of this synthesis mode");
   if (o->n_host < 1) return o->fail(HWO_ESTATE, "time_stage needs a completed step");
   int rc = collect_timing(o);
   if (rc) return rc;
@@ -1132,7 +1224,7 @@ int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep
   HWO_CHECK(hipEventCreate(&b));
   HWO_CHECK(hipEventRecord(a, o->st));
   for (int k = 0; k < reps; ++k) {
-    if (stage == ST_FFT_A || stage == ST_FFT_B) launch_stage(o, stage, nullptr);
+    if (stage == ST_FFT_A || stage == ST_FFT_B || layer_stage) launch_stage(o, stage, nullptr);
     else
       for (const auto &gp : groups) launch_stage(o, stage, &gp);
   }

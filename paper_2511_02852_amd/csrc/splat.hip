@@ -51,13 +51,6 @@ __device__ __forceinline__ float wrev(float q) {
   return (fabsf(q) < 0.25f) ? c * c : 0.f;
 }
 
-struct TileGeom {
-  int p, i0, j0, tw, th;
-  float Ab;            // boundary amplitude of the bucket being splatted
-  int64_t X0, Y0;      // first cell centre (position units)
-  float inv_dxu;
-};
-
 // Decode a particle record: crest centre in tile cell coordinates, amplitude, direction.
 template <class Rec>
 __device__ __forceinline__ bool load_item(const Dev &d, const Rec &r, int64_t n, int b, const TileGeom &T, float &cx,
@@ -77,56 +70,6 @@ __device__ __forceinline__ bool load_item(const Dev &d, const Rec &r, int64_t n,
 
 }  // namespace
 
-namespace {
-
-__device__ __forceinline__ int patch_of_tile(const Dev &d, int tile) {
-  int lo = 0, hi = d.np - 1;   // last patch with tile0 <= tile
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (d.patches[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ void tile_geom(const Dev &d, int tile, int p, TileGeom &T) {
-  const PatchDev &P = d.patches[p];
-  const StepPatch &W = d.sp[p];
-  T.p = p;
-  const int lt = tile - P.tile0;
-  T.i0 = (lt % P.ntx) * kTile;
-  T.j0 = (lt / P.ntx) * kTile;
-  T.tw = min(kTile, P.nx - T.i0);
-  T.th = min(kTile, P.ny - T.j0);
-  T.X0 = ((int64_t)W.wx + T.i0) * P.dxu + P.dxu / 2;
-  T.Y0 = ((int64_t)W.wy + T.j0) * P.dxu + P.dxu / 2;
-  T.inv_dxu = 1.0f / (float)P.dxu;
-}
-
-// Blend one cell (tile-local i, j) and store the raw and blended heights.
-__device__ __forceinline__ void blend_store(const Dev &d, const PatchDev &P, const StepPatch &W, const TileGeom &T,
-                                            int i, int j, float h, float *__restrict__ raw_out,
-                                            float *__restrict__ blend_out, int64_t out_off) {
-  const int ci = T.i0 + i, cj = T.j0 + j;
-  const size_t o = (size_t)(P.cell0 - out_off) + (size_t)cj * P.nx + ci;
-  raw_out[o] = h;
-  if (!blend_out) return;
-  const int N = d.N;
-  const float dx = (float)P.dx;
-  const float dd = fminf(fminf((float)ci + 0.5f, (float)P.nx - (float)ci - 0.5f),
-                         fminf((float)cj + 0.5f, (float)P.ny - (float)cj - 0.5f)) * dx;
-  const float t = fminf(dd * P.inv_band, 1.f);
-  const float s = t * t * (3.f - 2.f * t);
-  const float uu = W.fx0 + (float)ci * P.ratio, vv = W.fy0 + (float)cj * P.ratio;
-  const float fu = floorf(uu), fv = floorf(vv);
-  const float a = uu - fu, bb = vv - fv;
-  const int x0 = (W.gx0 + (int)fu) & (N - 1), y0 = (W.gy0 + (int)fv) & (N - 1);
-  const int x1 = (x0 + 1) & (N - 1), y1 = (y0 + 1) & (N - 1);
-  const float *Hr0 = d.H + (size_t)y0 * N, *Hr1 = d.H + (size_t)y1 * N;
-  const float hb = (1.f - bb) * ((1.f - a) * Hr0[x0] + a * Hr0[x1]) + bb * ((1.f - a) * Hr1[x0] + a * Hr1[x1]);
-  blend_out[o] = s * h + (1.f - s) * hb;
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------- load
 // Relative cost of one particle visit (decode plus footprint work) by path:
