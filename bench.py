@@ -99,8 +99,32 @@ def splat_flops(ocean, scene):
     return flops
 
 
+def layer_work(ocean, scene, rec_bytes, n_live):
+    """Algorithmic flops and bytes of the texel-layer stages.  Per (patch,
+    bucket) the layer spans the patch plus R = ceil(r / dx) - 1 cells each
+    side; the x pass makes (ny + 2R) nx outputs and the y pass ny nx, each a
+    (2R + 1)-tap multiply-add.  deposit_x reads every record once and writes
+    the x-filtered layers; filter_y reads them and writes one plane per
+    bucket; layer_sum reads the planes and writes the two maps."""
+    r = ocean.buckets()[:, 2]
+    fx = fy = bx = by = bs = 0.0
+    for P in scene.patches:
+        for ri in r:
+            R = max(0, math.ceil(ri / P.dx) - 1)
+            rows = P.ny + 2 * R
+            fx += 2.0 * rows * P.nx * (2 * R + 1)
+            fy += 2.0 * P.ny * P.nx * (2 * R + 1)
+            bx += 4.0 * rows * P.nx
+            by += 4.0 * rows * P.nx + 4.0 * P.nx * P.ny
+            bs += 4.0 * P.nx * P.ny
+        bs += 8.0 * P.nx * P.ny
+    bx += n_live * rec_bytes
+    return {"deposit_x": (fx, bx), "filter_y": (fy, by), "layer_sum": (0.0, bs)}
+
+
 DOM_KERNEL = {"splat": "k_splat<RecCompact>", "fft_a": "k_fft_a", "fft_b": "k_fft_b",
-              "count": "k_update<RecCompact, false>", "scatter": "k_update<RecCompact, true>"}
+              "count": "k_update<RecCompact, false>", "scatter": "k_update<RecCompact, true>",
+              "deposit_x": "k_deposit_x<RecCompact>", "filter_y": "k_filter_y", "layer_sum": "k_layer_sum"}
 
 
 def measured_traffic(config, dom):
@@ -194,6 +218,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=0)
     ap.add_argument("--trends", action="store_true",
                     help="paper-default scene over wind speeds and sampling densities (Table 2 trends)")
+    ap.add_argument("--synth", type=int, default=0,
+                    help="height synthesis: 0 exact-position splat, 1 the paper's texel layers")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -215,7 +241,8 @@ def main():
                           "unit": "ms/frame", "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "data": "synthetic", "trends": rows}), flush=True)
         return
-    scene = scenes.get(args.config)
+    scene = scenes.get(args.config).replace(synth=args.synth)
+    layers = args.synth == 1
     preroll = PREROLL.get(args.config, 0)
     K, W = args.steps, args.warmup
 
@@ -248,9 +275,12 @@ def main():
     gt.set_timing(False)
     live_t = live_total(gt, scene)
     flops = splat_flops(gt, scene)
+    lw = layer_work(gt, scene, g.record_bytes, live_t) if layers else None
     # kernels that can be re-launched on the finished frame: mean time per
     # launch over back-to-back launches (no per-launch event overhead)
-    rep_ms = {k: gt.time_stage(k, 20) for k in ("fft_a", "fft_b", "splat", "splat_plan", "splat_reduce")}
+    rep = ("fft_a", "fft_b", "deposit_x", "filter_y", "layer_sum") if layers else \
+        ("fft_a", "fft_b", "splat", "splat_plan", "splat_reduce")
+    rep_ms = {k: gt.time_stage(k, 20) for k in rep}
     gt.close()
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st.items()}
     per_launch.update(rep_ms)
@@ -263,18 +293,33 @@ def main():
     fft_ms = per_launch["fft_a"] + per_launch["fft_b"]
     fft_bytes = alg["fft_a"] + alg["fft_b"]
     fft_gbs = fft_bytes / (fft_ms * 1e-3) / 1e9 if fft_ms > 0 else None
-    splat_ms = per_launch["splat"]
+    splat_ms = (per_launch["deposit_x"] + per_launch["filter_y"] + per_launch["layer_sum"]) if layers \
+        else per_launch["splat"]
     splats_per_s = live_t / (splat_ms * 1e-3) if splat_ms > 0 else None
 
     # dominant kernel (largest time share) and its roofline: the roof whose
     # floor time (algorithmic bytes / 8 TB/s or flops / FP32 matrix peak) is
     # larger binds the kernel
-    dom = max(("fft_a", "fft_b", "count", "scatter", "splat"), key=lambda k: per_frame[k])
+    cands = ("fft_a", "fft_b", "count", "scatter") + (("deposit_x", "filter_y", "layer_sum") if layers else ("splat",))
+    dom = max(cands, key=lambda k: per_frame[k])
     t = per_launch[dom] * 1e-3
+    if layers and dom in lw:
+        flops_dom, alg[dom] = lw[dom]
+    else:
+        flops_dom = flops if dom == "splat" else 0.0
     t_hbm = alg[dom] / (HBM_PEAK_GBS * 1e9)
-    t_mfma = flops / (FP32_PEAK_TFLOPS * 1e12) if dom == "splat" else 0.0
-    traffic = measured_traffic(args.config, dom)
-    if t_mfma > t_hbm:
+    t_mfma = flops_dom / (FP32_PEAK_TFLOPS * 1e12)
+    traffic = measured_traffic(args.config + ("-layers" if layers else ""), dom)
+    if layers and t_mfma > t_hbm:
+        # the layer passes are FP32 vector multiply-adds (no matrix cores):
+        # bound by the vector ALUs, FP32 vector peak 157.3 TFLOP/s
+        achieved = flops_dom / t / 1e12 if t > 0 else 0.0
+        roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": traffic,
+                    "avg_launch_ms": round(per_launch[dom], 5), "algorithmic_flops_per_launch": int(flops_dom),
+                    "algorithmic_bytes_per_launch": int(alg[dom]),
+                    "hbm_frac": round(t_hbm / t, 5) if t > 0 else None}
+    elif t_mfma > t_hbm:
         achieved = flops / t / 1e12 if t > 0 else 0.0
         roofline = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": traffic,
@@ -326,6 +371,7 @@ def main():
                                f"{len(scene.patches)} patch(es), {scene.spectrum.n_buckets} buckets, "
                                f"frames {preroll + W + 1}..{preroll + W + K}",
                    "form": "16-byte records, batched launches, hipGraph",
+                   "synthesis": "texel layers + separable passes" if layers else "exact-position splat",
                    "live_particles": live, "preroll_frames": preroll},
         "splats_per_s": round(splats_per_s, 1) if splats_per_s else None,
         "fft_gbps": round(fft_gbs, 2) if fft_gbs else None,

@@ -182,11 +182,11 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * launch with HIP events (graph replay is then disabled); hwo_stage_times
  * returns accumulated milliseconds and launch counts per stage:
  *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat
- *   7 splat_plan  8 splat_reduce  9 bin_plan  10 layer_clear  11 deposit
- *   12 filter_x  13 filter_y (n >= 14).  bin_plan is the one-block scan +
- *   tile estimates + plan that replaces stages 4 and 7 in the batched form of
+ *   7 splat_plan  8 splat_reduce  9 bin_plan  10 deposit_x  11 filter_y
+ *   12 layer_sum (n >= 13).  bin_plan is the one-block scan + tile
+ *   estimates + plan that replaces stages 4 and 7 in the batched form of
  *   scenes with at most 65536 bins and 4096 tiles.  Stages 6-8 run with
- *   synth 0, stages 10-13 with synth 1. */
+ *   synth 0, stages 10-12 with synth 1. */
 int hwo_set_timing(hwo_ocean *o, int32_t enable);
 int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
 /* Benchmark support: after at least one step, launch the kernels of one
@@ -194,10 +194,9 @@ int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
  * and store the mean milliseconds per repetition (all launch groups of the
  * stage).  Only stages whose kernels are idempotent for a finished frame are
  * accepted: 1 fft_a, 2 fft_b, 6 splat, 7 splat_plan, 8 splat_reduce (synth 0),
- * 10 layer_clear, 12 filter_x, 13 filter_y (synth 1); any other stage gives
+ * 10 deposit_x, 11 filter_y, 12 layer_sum (synth 1); any other stage gives
  * HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are rewritten
- * with the same values (up to FP32 summation order), except that layer_clear
- * leaves the layers empty until the next step. */
+ * with the same values (up to FP32 summation order). */
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep);
 /* Bytes of particle storage per record for the active form (16 or 32). */
 int32_t hwo_record_bytes(const hwo_ocean *o);

@@ -86,9 +86,9 @@ struct PatchDev {
   uint64_t Rx[kMaxBuckets], Ry[kMaxBuckets];
   int32_t binu[kMaxBuckets];   // bin edge (position units)
   int32_t nbx[kMaxBuckets], nby[kMaxBuckets], binbase[kMaxBuckets];
-  // texel-layer synthesis: per bucket, the layer (patch plus lay_R cells on
-  // every side, row-major) and its x-filtered copy (patch columns only)
-  int64_t lay_off[kMaxBuckets], lt_off[kMaxBuckets];
+  // texel-layer synthesis: per bucket, the x-filtered layer (rows of the
+  // patch plus lay_R cells on every side, patch columns, row-major)
+  int64_t lt_off[kMaxBuckets];
   int32_t lay_R[kMaxBuckets], tap_off[kMaxBuckets];
 };
 
@@ -168,14 +168,14 @@ struct Dev {
   uint32_t chunk_load;         // least estimated cost of a work item
   // texel-layer synthesis (synth == 1)
   int32_t synth;
-  int32_t nlayer_rows;         // rows of all layers
-  int64_t lay_n;               // floats in all layers (multiple of 4)
-  float *lay;                  // layers, all patches and buckets
+  int32_t n_xtiles;            // 64 x 64 tiles of all x-filtered layers
+  int64_t ncells;              // cells of all patches
   float *lt;                   // x-filtered layers
+  float *yplanes;              // [nb][ncells] per-bucket maps after the y pass
   const float *taps;           // raised cosine at whole-cell offsets, 2R+1 per (patch, bucket)
-  const int32_t *row_base;     // [np * nb + 1] first layer row of each (patch, bucket)
+  const int32_t *xt_base;      // [np * nb + 1] first x tile of each (patch, bucket)
   const int2 *toff;            // [nb][kNCode] trough offset round(r (cos, sin) 2^20)
-  int32_t xsmem, ysmem;        // dynamic LDS bytes of the two passes
+  int32_t lsmem;               // dynamic LDS bytes of the layer passes
 };
 
 // ---------------------------------------------------------------- helpers
@@ -342,10 +342,10 @@ void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int
 void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, hipStream_t st);
 // Texel-layer synthesis.
 hipError_t prepare_layers(const Dev &d);
-void launch_layer_clear(const Dev &d, hipStream_t st);
-void launch_deposit(const Dev &d, const void *recs, int n, hipStream_t st);
-void launch_filter_x(const Dev &d, hipStream_t st);
-void launch_filter_y(const Dev &d, int t0, int ntiles, float *raw, float *blend, int64_t out_off, hipStream_t st);
+void launch_deposit_x(const Dev &d, const void *recs, int n, hipStream_t st);
+void launch_filter_y(const Dev &d, int t0, int ntiles, hipStream_t st);
+void launch_layer_sum(const Dev &d, int p0, int p1, int64_t cells, float *raw, float *blend, int64_t out_off,
+                      hipStream_t st);
 int scan_blocks(int nbins);
 
 }  // namespace hwo

@@ -37,9 +37,9 @@ namespace {
 constexpr double kUnit = 1048576.0;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kTwo30 = 1073741824.0;
-constexpr int kStages = 14;
+constexpr int kStages = 13;
 enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE, ST_BINPLAN,
-       ST_LCLEAR, ST_DEPOSIT, ST_FILTX, ST_FILTY };
+       ST_DEPX, ST_FILTY, ST_LSUM };
 
 int64_t pmod(int64_t a, int64_t m) {
   int64_t r = a % m;
@@ -77,10 +77,10 @@ struct hwo_ocean {
   std::vector<float> afac;         // [nb][kNCode] sqrt(2 pi Dir); stratified directions only
   // texel-layer synthesis tables
   std::vector<float> taps;         // 2R+1 raised-cosine taps per (patch, bucket)
-  std::vector<int32_t> row_base;   // first layer row per (patch, bucket), np*nb+1
+  std::vector<int32_t> xt_base;    // first x tile per (patch, bucket), np*nb+1
   std::vector<int2> toff;          // [nb][kNCode] trough offsets (units)
-  int64_t lay_total = 0, lt_total = 0;
-  int32_t max_R = 0, max_nx = 0;
+  int64_t lt_total = 0;
+  int32_t max_R = 0;
   std::vector<int2> V;             // [nb][kNCode]
   std::vector<float2> UC;          // [kNCode]
   // scene tables
@@ -440,11 +440,10 @@ static int build_scene_tables(hwo_ocean *o) {
   int64_t bins = 0, tiles = 0, cells = 0;
   const bool layers = o->cfg.synth == 1;
   o->taps.clear();
-  o->row_base.clear();
-  o->lay_total = o->lt_total = 0;
+  o->xt_base.clear();
+  o->lt_total = 0;
   o->max_R = 0;
-  o->max_nx = 0;
-  int64_t rows = 0;
+  int64_t xtiles = 0;
   const double dxf = o->cfg.fft_L / (double)o->cfg.fft_n;
   for (int p = 0; p < np; ++p) {
     const hwo_patch &hp = o->patches[p];
@@ -493,23 +492,20 @@ static int build_scene_tables(hwo_ocean *o) {
         const int64_t Rl = std::max<int64_t>(0, (int64_t)ceil(o->r[i] / hp.dx) - 1);
         if (Rl > 2048) return o->fail(HWO_EINVAL, "bucket radius too large for texel layers");
         P.lay_R[i] = (int32_t)Rl;
-        P.lay_off[i] = o->lay_total;
         P.lt_off[i] = o->lt_total;
         P.tap_off[i] = (int32_t)o->taps.size();
-        o->lay_total += ((int64_t)hp.nx + 2 * Rl) * ((int64_t)hp.ny + 2 * Rl);
         o->lt_total += (int64_t)hp.nx * ((int64_t)hp.ny + 2 * Rl);
         for (int64_t k = -Rl; k <= Rl; ++k) {
           const double dk = (double)k * hp.dx;
           o->taps.push_back((float)(fabs(dk) >= o->r[i] ? 0.0 : 0.5 * (1.0 + cos(M_PI * dk / o->r[i]))));
         }
-        o->row_base.push_back((int32_t)rows);
-        rows += (int64_t)hp.ny + 2 * Rl;
+        o->xt_base.push_back((int32_t)xtiles);
+        xtiles += (((int64_t)hp.ny + 2 * Rl + kTile - 1) / kTile) * (((int64_t)hp.nx + kTile - 1) / kTile);
         o->max_R = std::max(o->max_R, (int32_t)Rl);
-        if (rows > ((int64_t)1 << 30) || o->lay_total > ((int64_t)1 << 34))
+        if (xtiles > ((int64_t)1 << 30) || o->lt_total > ((int64_t)1 << 34))
           return o->fail(HWO_EINVAL, "texel layers too large");
       }
     }
-    o->max_nx = std::max(o->max_nx, (int32_t)hp.nx);
     P.bin_hi = (int32_t)bins;
     P.ntx = (hp.nx + kTile - 1) / kTile;
     P.nty = (hp.ny + kTile - 1) / kTile;
@@ -519,7 +515,7 @@ static int build_scene_tables(hwo_ocean *o) {
     P.cell0 = cells;
     cells += (int64_t)hp.nx * hp.ny;
   }
-  if (layers) o->row_base.push_back((int32_t)rows);
+  if (layers) o->xt_base.push_back((int32_t)xtiles);
   // source ranges per patch in sorted order
   for (int p = 0; p < np; ++p) {
     int lo = 0;
@@ -730,7 +726,8 @@ static int finalize(hwo_ocean *o) {
   d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
   d.synth = o->cfg.synth;
   if (d.synth == 1 && np > 0) {
-    d.nlayer_rows = o->row_base.back();
+    d.n_xtiles = o->xt_base.back();
+    d.ncells = cells;
     // trough offsets round(r (cos, sin) 2^20): the texel a trough lands in is an integer decision
     o->toff.resize((size_t)nb * kNCode);
     for (int b = 0; b < nb; ++b)
@@ -739,22 +736,22 @@ static int finalize(hwo_ocean *o) {
         o->toff[(size_t)b * kNCode + code] =
             make_int2((int32_t)llround(o->r[b] * cos(ang) * kUnit), (int32_t)llround(o->r[b] * sin(ang) * kUnit));
       }
-    d.lay_n = (o->lay_total + 3) & ~(int64_t)3;
-    d.lay = (float *)o->alloc(sizeof(float) * (size_t)d.lay_n);
     d.lt = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(o->lt_total, 1));
+    d.yplanes = (float *)o->alloc(sizeof(float) * (size_t)nb * (size_t)std::max<int64_t>(cells, 1));
     d.taps = upload(o, o->taps, &rc);
-    d.row_base = upload(o, o->row_base, &rc);
+    d.xt_base = upload(o, o->xt_base, &rc);
     d.toff = upload(o, o->toff, &rc);
     if (rc) return rc;
-    if (!d.lay || !d.lt) return o->fail(HWO_ENOMEM, "device allocation failed");
-    const int64_t xs = sizeof(float) * ((int64_t)o->max_nx + 2 * o->max_R + 2 * o->max_R + 1);
-    const int64_t ys = sizeof(float) * (((int64_t)kTile + 2 * o->max_R) * kTile + 2 * o->max_R + 1);
-    if (xs > 160 * 1024 || ys > 160 * 1024) return o->fail(HWO_EINVAL, "texel-layer filter does not fit in LDS");
-    d.xsmem = (int32_t)xs;
-    d.ysmem = (int32_t)ys;
+    if (!d.lt || !d.yplanes) return o->fail(HWO_ENOMEM, "device allocation failed");
+    // both passes stage (64 + 2R + 17) x 64 floats (the register-blocked FIR
+    // reads up to 16 rows / columns past the strip, zero padded) and the taps
+    // padded to a multiple of 16
+    const int64_t ls = sizeof(float) * (((int64_t)kTile + 2 * o->max_R + 17) * kTile + 2 * o->max_R + 17);
+    if (ls > 160 * 1024) return o->fail(HWO_EINVAL, "texel-layer passes do not fit in LDS (bucket radius too large)");
+    d.lsmem = (int32_t)ls;
     HWO_CHECK(prepare_layers(d));
-    HWO_CHECK(hipMemsetAsync(d.lay, 0, sizeof(float) * (size_t)d.lay_n, o->st));
     HWO_CHECK(hipMemsetAsync(d.lt, 0, sizeof(float) * (size_t)std::max<int64_t>(o->lt_total, 1), o->st));
+    HWO_CHECK(hipMemsetAsync(d.yplanes, 0, sizeof(float) * (size_t)nb * (size_t)std::max<int64_t>(cells, 1), o->st));
   }
   if (!d.tile_load || !d.tile_meas || !d.tile_model || !d.tile_ratio || !d.item_base || !d.splat_ctl ||
       !d.split_tiles || !d.partials)
@@ -816,10 +813,9 @@ static void launch_stage(hwo_ocean *o, int stage, const PatchArg *g) {
       break;
     case ST_REDUCE: launch_splat_reduce(d, g->t0, g->t1 - g->t0, o->st); break;
     case ST_BINPLAN: launch_bin_plan(d, d.nbins, d.ntiles, o->items_target, o->st); break;
-    case ST_LCLEAR: launch_layer_clear(d, o->st); break;
-    case ST_DEPOSIT: launch_deposit(d, nullptr, 0, o->st); break;
-    case ST_FILTX: launch_filter_x(d, o->st); break;
-    case ST_FILTY: launch_filter_y(d, 0, d.ntiles, d.raw, d.blend, 0, o->st); break;
+    case ST_DEPX: launch_deposit_x(d, nullptr, 0, o->st); break;
+    case ST_FILTY: launch_filter_y(d, 0, d.ntiles, o->st); break;
+    case ST_LSUM: launch_layer_sum(d, 0, d.np, d.ncells, d.raw, d.blend, 0, o->st); break;
     default: break;
   }
 }
@@ -897,13 +893,12 @@ static void run_step(hwo_ocean *o) {
       }
     }
     if (layers) {
-      // texel layers of all patches: deposit, pass along x, then (with the
-      // background) pass along y, layer sum and blend
-      timed(o, ST_LCLEAR, nullptr);
-      timed(o, ST_DEPOSIT, nullptr);
-      timed(o, ST_FILTX, nullptr);
-      join();
+      // texel layers of all patches: deposit and pass along x, pass along y,
+      // then (with the background) the layer sum and blend
+      timed(o, ST_DEPX, nullptr);
       timed(o, ST_FILTY, nullptr);
+      join();
+      timed(o, ST_LSUM, nullptr);
     } else if (o->fused) {
       join();
       timed(o, ST_SPLAT, &groups[0]);
@@ -1167,10 +1162,9 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
   hipError_t e = hipMemcpyAsync(drec, host.data(), host.size(), hipMemcpyHostToDevice, o->st);
   if (e == hipSuccess) {
     if (d.synth == 1) {
-      launch_layer_clear(d, o->st);
-      launch_deposit(d, drec, (int)n, o->st);
-      launch_filter_x(d, o->st);
-      launch_filter_y(d, P.tile0, P.ntx * P.nty, dout, nullptr, P.cell0, o->st);
+      launch_deposit_x(d, drec, (int)n, o->st);
+      launch_filter_y(d, P.tile0, P.ntx * P.nty, o->st);
+      launch_layer_sum(d, patch, patch + 1, cells, dout, nullptr, P.cell0, o->st);
     } else {
       launch_splat_direct(d, P.tile0, P.ntx * P.nty, drec, (int)n, dout, P.cell0, o->st);
     }
@@ -1210,7 +1204,7 @@ int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n) {
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep) {
   if (!o || !ms_per_rep || reps < 1) return HWO_EINVAL;
   const bool splat_stage = stage == ST_PLAN || stage == ST_SPLAT || stage == ST_REDUCE;
-  const bool layer_stage = stage == ST_LCLEAR || stage == ST_FILTX || stage == ST_FILTY;
+  const bool layer_stage = stage == ST_DEPX || stage == ST_FILTY || stage == ST_LSUM;
   if (stage != ST_FFT_A && stage != ST_FFT_B && !splat_stage && !layer_stage)
     return o->fail(HWO_EINVAL, "stage is not repeatable (it advances or consumes state)");
   if ((splat_stage && o->cfg.synth == 1) || (layer_stage && o->cfg.synth != 1))

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libhwo.so")
 
 HWO_OK, HWO_EINVAL, HWO_ESTATE, HWO_ENOMEM, HWO_EDEVICE, HWO_ERANGE, HWO_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
 STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "splat_plan", "splat_reduce",
-          "bin_plan", "layer_clear", "deposit", "filter_x", "filter_y"]
+          "bin_plan", "deposit_x", "filter_y", "layer_sum"]
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",

@@ -87,9 +87,9 @@ def test_call_order_errors(L):
     assert L.hwo_read_buckets(h, buf, 64) == hwo.HWO_ESTATE   # before set_spectrum
     ms = C.c_double()
     # only idempotent stages can be re-launched, and only after a step
-    for stage in (0, 3, 4, 5, 11):   # params, count, scan, scatter, deposit
+    for stage in (0, 3, 4, 5, 13):   # params, count, scan, scatter, no such stage
         assert L.hwo_time_stage(h, stage, 5, C.byref(ms)) == hwo.HWO_EINVAL
-    for stage in (10, 12, 13):   # layer stages need synth 1
+    for stage in (10, 11, 12):   # layer stages need synth 1
         assert L.hwo_time_stage(h, stage, 5, C.byref(ms)) == hwo.HWO_EINVAL
     assert L.hwo_time_stage(h, 6, 5, C.byref(ms)) == hwo.HWO_ESTATE
     assert L.hwo_time_stage(h, 6, 0, C.byref(ms)) == hwo.HWO_EINVAL
