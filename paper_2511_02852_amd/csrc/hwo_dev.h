@@ -174,6 +174,9 @@ struct Dev {
   float *yplanes;              // [nb][ncells] per-bucket maps after the y pass
   const float *taps;           // raised cosine at whole-cell offsets, 2R+1 per (patch, bucket)
   const int32_t *xt_base;      // [np * nb + 1] first x tile of each (patch, bucket)
+  int32_t xparts;              // most parts per x tile (1: no cutting)
+  int32_t *xt_nparts;          // [n_xtiles] parts of each x tile this frame
+  float *xpartial;             // [n_xtiles][xparts][64 * 64] partial x-filtered tiles
   const int2 *toff;            // [nb][kNCode] trough offset round(r (cos, sin) 2^20)
   int32_t lsmem;               // dynamic LDS bytes of the layer passes
 };

@@ -33,6 +33,9 @@ namespace {
 
 constexpr int kRowsPerThread = kTile * kTile / kThreads;   // 16
 constexpr int kBatch = 4;                                   // particles in flight per thread (deposit)
+// A part costs its particles plus one x pass, so only tiles far above a
+// typical load are cut (the wake rings of a source crowd a few tiles).
+constexpr int kPartLoad = 4096;                             // particles per part of a heavy layer tile
 
 // Bilinear deposit of amplitude A at window-relative position (x, y) (units)
 // into the LDS window D of columns [tx0, tx0 + dw) and rows [ty0, ty0 + dh)
@@ -116,7 +119,13 @@ template <class Rec>
 __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__restrict__ direct, int ndirect) {
   extern __shared__ float xs[];
   __shared__ int s_rlo[64], s_pre[65];
-  const int k = blockIdx.x;
+  __shared__ int s_total;
+  // block = (x tile, part); a tile whose bins hold many particles is cut
+  // into up to d.xparts parts of about kPartLoad particles, each writing a
+  // partial tile that the y pass sums.  Part 0 of every tile comes first in
+  // the grid, the blocks of further parts (most of which exit at once) last.
+  const int part = (int)blockIdx.x / d.n_xtiles;
+  const int k = (int)blockIdx.x - part * d.n_xtiles;
   const int l = layer_of_xtile(d, k);
   const int p = l / d.nb, b = l - p * d.nb;
   const PatchDev &P = d.patches[p];
@@ -133,11 +142,39 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
   const int pitch = kTile + 2 * R + 17;                     // odd: column reads across rows are conflict-free
   float *D = xs;
   float *s_w = xs + kTile * pitch;
+  const int64_t n = d.glob->n;
+  const float inv_dxu = 1.0f / (float)P.dxu;
+  // crests whose crest or trough can land in D: window-relative x in
+  // [xa - ru, xb + ru) with ru >= |trough offset|; bins are anchored at the
+  // window origin minus the survival margin m
+  const int64_t m = d.margin[b], binu = P.binu[b];
+  const int64_t ru = (int64_t)(d.bucket_r[b] * 1048576.0f * 1.000001f) + 2;
+  const int64_t xa = (int64_t)(tx0 - 1 - R) * P.dxu + P.dxu / 2, xb = (int64_t)(tx0 + dw - R) * P.dxu + P.dxu / 2;
+  const int64_t ya = (int64_t)(ty0 - 1 - R) * P.dxu + P.dxu / 2, yb = (int64_t)(ty0 + dh - R) * P.dxu + P.dxu / 2;
+  const int bx_lo = (int)max<int64_t>(0, floor_div(xa - ru + m, binu));
+  const int bx_hi = (int)min<int64_t>(P.nbx[b] - 1, floor_div(xb + ru + m, binu));
+  const int by_lo = (int)max<int64_t>(0, floor_div(ya - ru + m, binu));
+  const int by_hi = (int)min<int64_t>(P.nby[b] - 1, floor_div(yb + ru + m, binu));
+  // particles in the bin rectangle (one wavefront), hence the parts
+  if (threadIdx.x < 64) {
+    int tot = 0;
+    if (!direct && bx_lo <= bx_hi)
+      for (int by = by_lo + (int)threadIdx.x; by <= by_hi; by += 64) {
+        const int rb = P.binbase[b] + by * P.nbx[b];
+        tot += max(0, min(d.off[rb + bx_hi + 1], d.cap) - min(d.off[rb + bx_lo], d.cap));
+      }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (threadIdx.x == 0) s_total = tot;
+  }
+  __syncthreads();
+  const int M = s_total;
+  const int nparts = direct ? 1 : max(1, min(d.xparts, (M + kPartLoad - 1) / kPartLoad));
+  if (part >= nparts) return;   // block-uniform
+  if (part == 0 && threadIdx.x == 0) d.xt_nparts[k] = nparts;
+  const int e_lo = (int)((int64_t)M * part / nparts), e_hi = (int)((int64_t)M * (part + 1) / nparts);
   for (int e = threadIdx.x; e < kTile * pitch; e += kThreads) D[e] = 0.f;
   for (int e = threadIdx.x; e < K16; e += kThreads) s_w[e] = e < nt ? d.taps[P.tap_off[b] + e] : 0.f;
   __syncthreads();
-  const int64_t n = d.glob->n;
-  const float inv_dxu = 1.0f / (float)P.dxu;
   if (direct) {
     for (int e = threadIdx.x; e < ndirect; e += kThreads) {
       const Part q = RecIO<Rec>::unpack(direct[e], n);
@@ -145,22 +182,12 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
         deposit_rec<Rec>(d, direct[e], n, b, P, Wp, D, pitch, tx0, ty0, dw, dh, R, inv_dxu);
     }
   } else {
-    // crests whose crest or trough can land in D: window-relative x in
-    // [xa - ru, xb + ru) with ru >= |trough offset|; bins are anchored at the
-    // window origin minus the survival margin m
     const Rec *__restrict__ S = (const Rec *)((n & 1) ? d.S1 : d.S0);
-    const int64_t m = d.margin[b], binu = P.binu[b];
-    const int64_t ru = (int64_t)(d.bucket_r[b] * 1048576.0f * 1.000001f) + 2;
-    const int64_t xa = (int64_t)(tx0 - 1 - R) * P.dxu + P.dxu / 2, xb = (int64_t)(tx0 + dw - R) * P.dxu + P.dxu / 2;
-    const int64_t ya = (int64_t)(ty0 - 1 - R) * P.dxu + P.dxu / 2, yb = (int64_t)(ty0 + dh - R) * P.dxu + P.dxu / 2;
-    const int bx_lo = (int)max<int64_t>(0, floor_div(xa - ru + m, binu));
-    const int bx_hi = (int)min<int64_t>(P.nbx[b] - 1, floor_div(xb + ru + m, binu));
-    const int by_lo = (int)max<int64_t>(0, floor_div(ya - ru + m, binu));
-    const int by_hi = (int)min<int64_t>(P.nby[b] - 1, floor_div(yb + ru + m, binu));
     // up to 64 bin rows at a time: row lengths, their prefix (one wavefront),
-    // then every thread takes particles of the flattened list, so that the
-    // record loads of a block are independent
-    for (int r0 = by_lo; r0 <= by_hi && bx_lo <= bx_hi; r0 += 64) {   // block-uniform
+    // then every thread takes particles of the flattened list that fall in
+    // this part, so that the record loads of a block are independent
+    int g0 = 0;   // flattened index of the chunk's first particle
+    for (int r0 = by_lo; r0 <= by_hi && bx_lo <= bx_hi && g0 < e_hi; r0 += 64) {   // block-uniform
       const int nr = min(64, by_hi - r0 + 1);
       if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
@@ -181,14 +208,16 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
       }
       __syncthreads();
       const int total = s_pre[64];
+      const int c_lo = max(0, e_lo - g0), c_hi = min(total, e_hi - g0);
+      g0 += total;
       // kBatch particles per thread per round: their record loads, then their
       // table loads, are issued together before any deposit
-      for (int e0 = 0; e0 < total; e0 += kThreads * kBatch) {
+      for (int e0 = c_lo; e0 < c_hi; e0 += kThreads * kBatch) {
         Rec rr[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
           const int e = e0 + j * kThreads + (int)threadIdx.x;
-          if (e < total) {
+          if (e < c_hi) {
             int lo = 0, hi = nr - 1;   // last row with prefix <= e
             while (lo < hi) {
               const int mid = (lo + hi + 1) >> 1;
@@ -202,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
         float A[kBatch];
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-          if (e0 + j * kThreads + (int)threadIdx.x < total) {
+          if (e0 + j * kThreads + (int)threadIdx.x < c_hi) {
             q[j] = RecIO<Rec>::unpack(rr[j], n);
             v[j] = d.V[b * kNCode + q[j].code];
             to[j] = d.toff[b * kNCode + q[j].code];
@@ -211,7 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
         }
 #pragma unroll
         for (int j = 0; j < kBatch; ++j) {
-          if (e0 + j * kThreads + (int)threadIdx.x < total) {
+          if (e0 + j * kThreads + (int)threadIdx.x < c_hi) {
             const int64_t px = (int64_t)q[j].ox + (((int64_t)q[j].age * v[j].x) >> 12);
             const int64_t py = (int64_t)q[j].oy + (((int64_t)q[j].age * v[j].y) >> 12);
             const int64_t x = px - (int64_t)Wp.wx * P.dxu, y = py - (int64_t)Wp.wy * P.dxu;
@@ -234,7 +263,8 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
     for (int u = 0; u < 16; ++u) acc[u] = 0.f;
     const float *src = D + row * pitch + c0;
     fir16(s_w, K16, [&](int i) { return src[i]; }, acc);
-    float *dst = d.lt + P.lt_off[b] + (size_t)(ty0 + row) * P.nx + tx0 + c0;
+    float *dst = (nparts == 1) ? d.lt + P.lt_off[b] + (size_t)(ty0 + row) * P.nx + tx0 + c0
+                               : d.xpartial + ((size_t)k * d.xparts + part) * (kTile * kTile) + row * kTile + c0;
 #pragma unroll
     for (int u = 0; u < 16; ++u)
       if (c0 + u < tw) dst[u] = acc[u];
@@ -256,11 +286,31 @@ __global__ __launch_bounds__(kThreads) void k_filter_y(Dev d, int t0) {
   const int srows = kTile + 2 * R + 17;   // rows read by the register-blocked pass, zero beyond `rows`
   float *s_t = ys;
   float *s_w = ys + srows * kTile;
-  // rows j0 .. j0 + th + 2R - 1 of the x-filtered layer (patch rows j - R)
+  // rows j0 .. j0 + th + 2R - 1 of the x-filtered layer (patch rows j - R);
+  // rows of a tile cut into parts are the sum of its partial tiles
   const float *src = d.lt + P.lt_off[b] + (size_t)T.j0 * P.nx + T.i0;
+  const int xbase = d.xt_base[p * d.nb + b] + T.i0 / kTile;
+  const int ntc = (P.nx + kTile - 1) / kTile;
+  __shared__ int s_np[16];   // parts of the x tiles the strip crosses (the LDS budget keeps R <= 279: <= 10 tiles)
+  const int xr0 = T.j0 / kTile;
+  if (threadIdx.x < 16 && (T.j0 + rows - 1) / kTile >= xr0 + (int)threadIdx.x)
+    s_np[threadIdx.x] = d.xt_nparts[xbase + (xr0 + (int)threadIdx.x) * ntc];
+  __syncthreads();
   for (int e = threadIdx.x; e < srows * kTile; e += kThreads) {
     const int rr = e / kTile, cc = e - rr * kTile;
-    s_t[e] = (rr < rows && cc < T.tw) ? src[(size_t)rr * P.nx + cc] : 0.f;
+    float v = 0.f;
+    if (rr < rows && cc < T.tw) {
+      const int tr = T.j0 + rr;   // x-filtered layer row
+      const int xt = xbase + (tr / kTile) * ntc;
+      const int np = s_np[tr / kTile - xr0];
+      if (np <= 1) {
+        v = src[(size_t)rr * P.nx + cc];
+      } else {
+        const float *pp = d.xpartial + (size_t)xt * d.xparts * (kTile * kTile) + (tr % kTile) * kTile + cc;
+        for (int q = 0; q < np; ++q) v += pp[(size_t)q * (kTile * kTile)];
+      }
+    }
+    s_t[e] = v;
   }
   for (int i = threadIdx.x; i < K16; i += kThreads) s_w[i] = i < nt ? d.taps[P.tap_off[b] + i] : 0.f;
   __syncthreads();
@@ -315,12 +365,12 @@ hipError_t prepare_layers(const Dev &d) {
 
 void launch_deposit_x(const Dev &d, const void *recs, int n, hipStream_t st) {
   if (d.n_xtiles <= 0) return;
+  const int grid = d.n_xtiles * d.xparts;
   if (d.compact)
-    hipLaunchKernelGGL(k_deposit_x<RecCompact>, dim3(d.n_xtiles), dim3(kThreads), d.lsmem, st, d,
-                       (const RecCompact *)recs, n);
-  else
-    hipLaunchKernelGGL(k_deposit_x<RecWide>, dim3(d.n_xtiles), dim3(kThreads), d.lsmem, st, d, (const RecWide *)recs,
+    hipLaunchKernelGGL(k_deposit_x<RecCompact>, dim3(grid), dim3(kThreads), d.lsmem, st, d, (const RecCompact *)recs,
                        n);
+  else
+    hipLaunchKernelGGL(k_deposit_x<RecWide>, dim3(grid), dim3(kThreads), d.lsmem, st, d, (const RecWide *)recs, n);
 }
 
 void launch_filter_y(const Dev &d, int t0, int ntiles, hipStream_t st) {

@@ -737,6 +737,12 @@ static int finalize(hwo_ocean *o) {
             make_int2((int32_t)llround(o->r[b] * cos(ang) * kUnit), (int32_t)llround(o->r[b] * sin(ang) * kUnit));
       }
     d.lt = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(o->lt_total, 1));
+    // heavy x tiles are cut into up to four parts; the partial tiles take
+    // 64 KiB per x tile, so very large scenes keep one part per tile
+    d.xparts = ((int64_t)d.n_xtiles * 4 * kTile * kTile * 4 <= ((int64_t)1 << 30)) ? 4 : 1;
+    d.xt_nparts = (int32_t *)o->alloc(sizeof(int32_t) * (size_t)std::max(d.n_xtiles, 1));
+    d.xpartial = (float *)o->alloc(sizeof(float) * (size_t)std::max(d.n_xtiles, 1) * d.xparts * kTile * kTile);
+    if (!d.xt_nparts || !d.xpartial) return o->fail(HWO_ENOMEM, "device allocation failed");
     d.yplanes = (float *)o->alloc(sizeof(float) * (size_t)nb * (size_t)std::max<int64_t>(cells, 1));
     d.taps = upload(o, o->taps, &rc);
     d.xt_base = upload(o, o->xt_base, &rc);
@@ -747,10 +753,11 @@ static int finalize(hwo_ocean *o) {
     // reads up to 16 rows / columns past the strip, zero padded) and the taps
     // padded to a multiple of 16
     const int64_t ls = sizeof(float) * (((int64_t)kTile + 2 * o->max_R + 17) * kTile + 2 * o->max_R + 17);
-    if (ls > 160 * 1024) return o->fail(HWO_EINVAL, "texel-layer passes do not fit in LDS (bucket radius too large)");
+    if (ls > 159 * 1024) return o->fail(HWO_EINVAL, "texel-layer passes do not fit in LDS (bucket radius too large)");   // 1 KiB for static LDS
     d.lsmem = (int32_t)ls;
     HWO_CHECK(prepare_layers(d));
     HWO_CHECK(hipMemsetAsync(d.lt, 0, sizeof(float) * (size_t)std::max<int64_t>(o->lt_total, 1), o->st));
+    HWO_CHECK(hipMemsetAsync(d.xt_nparts, 0, sizeof(int32_t) * (size_t)std::max(d.n_xtiles, 1), o->st));
     HWO_CHECK(hipMemsetAsync(d.yplanes, 0, sizeof(float) * (size_t)nb * (size_t)std::max<int64_t>(cells, 1), o->st));
   }
   if (!d.tile_load || !d.tile_meas || !d.tile_model || !d.tile_ratio || !d.item_base || !d.splat_ctl ||
