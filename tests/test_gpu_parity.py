@@ -200,7 +200,8 @@ def test_obliquity_weighted_injection(name, steps, form):
     heights."""
     import dataclasses
     s = scenes.get(name)
-    s = s.replace(spectrum=dataclasses.replace(s.spectrum, flux_mode=1, wind_dir=0.4))
+    # obliquity weighting draws directions by inverse CDF (dir_mode 0)
+    s = s.replace(spectrum=dataclasses.replace(s.spectrum, flux_mode=1, dir_mode=0, wind_dir=0.4))
     kw = dict(compact=True, batched=True) if form == "batched" else {}
     say(f"obliquity {name} {form} {steps} steps")
     g, o = make(s, **kw)
