@@ -174,14 +174,14 @@ def bins_for(ocean, scene):
     return out
 
 
-def trends(K, W):
+def trends(K, W, synth=0):
     """The paper's default scene (U10 = 5, N_omega = N_theta = 16) over wind
     speed and sampling density, each run to the steady state of its slowest
     waves: the cost trends of the paper's parameter table."""
     import dataclasses
     import torch
     from paper_2511_02852_amd import hwo, scenes
-    base = scenes.p0()
+    base = scenes.p0().replace(synth=synth)
     runs = [(u, 16) for u in (3.0, 5.0, 10.0, 15.0)] + [(5.0, 8), (5.0, 12)]
     rows = []
     for u10, ns in runs:
@@ -236,8 +236,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if args.trends:
-        rows = trends(args.steps, args.warmup)
+        rows = trends(args.steps, args.warmup, args.synth)
         print(json.dumps({"metric": "ms/frame of the paper-default scene over U10 and (N_omega, N_theta)",
+                          "synthesis": "texel layers + separable passes" if args.synth else "exact-position splat",
                           "unit": "ms/frame", "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "data": "synthetic", "trends": rows}), flush=True)
         return

@@ -73,6 +73,9 @@ typedef struct {
                                texel layers (Sec 4.2) -- bilinear deposit per bucket,
                                passes along x and y with the raised cosine at
                                whole-cell offsets, layers summed */
+    int32_t normals;        /* 1: also derive unit normals of the blended maps by
+                               finite differences every frame (Sec 4.2), read as
+                               layers 2-4 of hwo_read_heightmaps; 0: none */
 } hwo_config;
 
 /* Spectrum and bucket parameters (Sec 3.1, Sec 3.3). */
@@ -145,7 +148,10 @@ int64_t hwo_step_index(const hwo_ocean *o);
 
 /* Copy a height map (FP32, row-major [y][x]) into dst (host or device memory
  * per dst_is_device).  which = -1: background N x N; which = p >= 0: patch p
- * (ny x nx) with layer 0 = blended, 1 = raw wave-particle height.  Syncs. */
+ * (ny x nx) with layer 0 = blended, 1 = raw wave-particle height, 2, 3, 4 =
+ * x, y, z component of the unit normal of the blended map (central
+ * differences, one-sided at the patch edges; HWO_ESTATE unless
+ * hwo_config.normals).  Syncs. */
 int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst,
                         int64_t dst_elems, int32_t dst_is_device);
 
@@ -183,7 +189,7 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * returns accumulated milliseconds and launch counts per stage:
  *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat
  *   7 splat_plan  8 splat_reduce  9 bin_plan  10 deposit_x  11 filter_y
- *   12 layer_sum (n >= 13).  bin_plan is the one-block scan + tile
+ *   12 layer_sum  13 normals (n >= 14).  bin_plan is the one-block scan + tile
  *   estimates + plan that replaces stages 4 and 7 in the batched form of
  *   scenes with at most 65536 bins and 4096 tiles.  Stages 6-8 run with
  *   synth 0, stages 10-12 with synth 1. */
@@ -194,7 +200,8 @@ int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
  * and store the mean milliseconds per repetition (all launch groups of the
  * stage).  Only stages whose kernels are idempotent for a finished frame are
  * accepted: 1 fft_a, 2 fft_b, 6 splat, 7 splat_plan, 8 splat_reduce (synth 0),
- * 10 deposit_x, 11 filter_y, 12 layer_sum (synth 1); any other stage gives
+ * 10 deposit_x, 11 filter_y, 12 layer_sum (synth 1), 13 normals (when
+ * enabled); any other stage gives
  * HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are rewritten
  * with the same values (up to FP32 summation order). */
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep);

@@ -58,6 +58,7 @@ def lib():
         "orc_add_source": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32]),
         "orc_set_bins": (C.c_int, [vp, P(i32)]),
         "orc_set_synthesis": (C.c_int, [vp, i32]),
+        "orc_normals": (C.c_int, [vp, i32, P(dbl), P(dbl)]),
         "orc_step": (C.c_int, [vp, i32]),
         "orc_step_index": (i64, [vp]),
         "orc_background": (C.c_int, [vp, P(dbl)]),
@@ -312,6 +313,14 @@ class Oracle:
         raw = np.ascontiguousarray(raw, dtype=np.float64)
         out = np.zeros_like(raw)
         self._check(self.L.orc_blend(self.h, p, _p(H, C.c_double), _p(raw, C.c_double), _p(out, C.c_double)))
+        return out
+
+    def normals(self, p: int, h: np.ndarray) -> np.ndarray:
+        """Unit normals (3, ny, nx) of patch p's map h by finite differences."""
+        pt = self.scene.patches[p]
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        out = np.zeros((3, pt.ny, pt.nx))
+        self._check(self.L.orc_normals(self.h, p, _p(h, C.c_double), _p(out, C.c_double)))
         return out
 
     def splat(self, p: int, recs: np.ndarray) -> np.ndarray:

@@ -1204,6 +1204,35 @@ int orc_blend(orc_ocean *o, int32_t p, const double *H, const double *raw, doubl
     return 0;
 }
 
+/* Sec 4.2: normals of a patch map by finite differences.  The slope along x
+ * at cell (i, j) is the central difference (h[i+1] - h[i-1]) / (2 dx), one-
+ * sided at the first and last column (zero for a single column); likewise
+ * along y.  The unit normal is (-sx, -sy, 1) / sqrt(1 + sx^2 + sy^2), stored
+ * as three ny x nx planes (x, y, z components). */
+int orc_normals(orc_ocean *o, int32_t p, const double *h, double *out) {
+    if (p < 0 || p >= o->np) return fail(o, "patch out of range");
+    if (!h || !out) return fail(o, "null map");
+    const patch_t *pt = &o->pt[p];
+    const int64_t nx = pt->nx, ny = pt->ny, nc = nx * ny;
+    for (int64_t j = 0; j < ny; ++j)
+        for (int64_t i = 0; i < nx; ++i) {
+            double sx = 0.0, sy = 0.0;
+            if (nx > 1) {
+                int64_t a = i > 0 ? i - 1 : i, b = i < nx - 1 ? i + 1 : i;
+                sx = (h[j * nx + b] - h[j * nx + a]) / ((double)(b - a) * pt->dx);
+            }
+            if (ny > 1) {
+                int64_t a = j > 0 ? j - 1 : j, b = j < ny - 1 ? j + 1 : j;
+                sy = (h[b * nx + i] - h[a * nx + i]) / ((double)(b - a) * pt->dx);
+            }
+            double inv = 1.0 / sqrt(1.0 + sx * sx + sy * sy);
+            out[j * nx + i] = -sx * inv;
+            out[nc + j * nx + i] = -sy * inv;
+            out[2 * nc + j * nx + i] = inv;
+        }
+    return 0;
+}
+
 /* Splat caller-placed particles (canonical records) into a patch map at the
  * current step; used by the closed-form pins. */
 int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *raw) {

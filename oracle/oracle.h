@@ -40,6 +40,9 @@ int orc_set_bins(orc_ocean *o, const int32_t *bin_cells);
 /* Height synthesis: 0 the exact-position separable splat, 1 texel layers per
  * bucket (bilinear deposit) smoothed by separable x and y passes (Sec 4.2). */
 int orc_set_synthesis(orc_ocean *o, int32_t mode);
+/* Unit normals of patch p from height map h (ny x nx) by finite differences
+ * (Sec 4.2); out holds three ny x nx planes: x, y and z components. */
+int orc_normals(orc_ocean *o, int32_t p, const double *h, double *out);
 int orc_step(orc_ocean *o, int32_t nsteps);
 int64_t orc_step_index(const orc_ocean *o);
 

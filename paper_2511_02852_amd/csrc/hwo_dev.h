@@ -179,6 +179,7 @@ struct Dev {
   float *xpartial;             // [n_xtiles][xparts][64 * 64] partial x-filtered tiles
   const int2 *toff;            // [nb][kNCode] trough offset round(r (cos, sin) 2^20)
   int32_t lsmem;               // dynamic LDS bytes of the layer passes
+  float *nrm;                  // [3][ncells] unit normals (x, y, z planes); null unless enabled
 };
 
 // ---------------------------------------------------------------- helpers
@@ -349,6 +350,8 @@ void launch_deposit_x(const Dev &d, const void *recs, int n, hipStream_t st);
 void launch_filter_y(const Dev &d, int t0, int ntiles, hipStream_t st);
 void launch_layer_sum(const Dev &d, int p0, int p1, int64_t cells, float *raw, float *blend, int64_t out_off,
                       hipStream_t st);
+// Finite-difference normals of the blended maps.
+void launch_normals(const Dev &d, hipStream_t st);
 int scan_blocks(int nbins);
 
 }  // namespace hwo

@@ -21,6 +21,8 @@
 //                16 rows of one column, the bucket's plane is stored.
 //   k_layer_sum  one thread per patch cell: the sum over the bucket planes,
 //                blended with the background and stored with the raw map.
+// k_normals (either synthesis, when enabled) derives unit normals from the
+// blended maps by finite differences.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -349,7 +351,45 @@ __global__ __launch_bounds__(kThreads) void k_layer_sum(Dev d, int p0, int p1, f
   }
 }
 
+// Normals of the blended maps by finite differences (Sec 4.2): central
+// differences inside, one-sided at the first and last row and column, unit
+// normal (-sx, -sy, 1) / sqrt(1 + sx^2 + sy^2); one thread per cell.
+__global__ __launch_bounds__(kThreads) void k_normals(Dev d) {
+  for (int64_t cell = (int64_t)blockIdx.x * kThreads + threadIdx.x; cell < d.ncells;
+       cell += (int64_t)gridDim.x * kThreads) {
+    int lo = 0, hi = d.np - 1;   // last patch with cell0 <= cell
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (d.patches[mid].cell0 <= cell) lo = mid; else hi = mid - 1;
+    }
+    const PatchDev &P = d.patches[lo];
+    const int64_t lc = cell - P.cell0;
+    const int i = (int)(lc % P.nx), j = (int)(lc / P.nx);
+    const float *h = d.blend + P.cell0;
+    const float inv_dx = (float)(1.0 / P.dx);
+    float sx = 0.f, sy = 0.f;
+    if (P.nx > 1) {
+      const int a = i > 0 ? i - 1 : i, b = i < P.nx - 1 ? i + 1 : i;
+      sx = (h[(size_t)j * P.nx + b] - h[(size_t)j * P.nx + a]) * inv_dx / (float)(b - a);
+    }
+    if (P.ny > 1) {
+      const int a = j > 0 ? j - 1 : j, b = j < P.ny - 1 ? j + 1 : j;
+      sy = (h[(size_t)b * P.nx + i] - h[(size_t)a * P.nx + i]) * inv_dx / (float)(b - a);
+    }
+    const float inv = 1.0f / sqrtf(1.f + sx * sx + sy * sy);
+    d.nrm[cell] = -sx * inv;
+    d.nrm[d.ncells + cell] = -sy * inv;
+    d.nrm[2 * d.ncells + cell] = inv;
+  }
+}
+
 }  // namespace
+
+void launch_normals(const Dev &d, hipStream_t st) {
+  if (!d.nrm || d.ncells <= 0) return;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((d.ncells + kThreads - 1) / kThreads, 16384));
+  hipLaunchKernelGGL(k_normals, dim3(grid), dim3(kThreads), 0, st, d);
+}
 
 hipError_t prepare_layers(const Dev &d) {
   // both passes stage up to (64 + 2R) x 64 floats, which can exceed the

@@ -37,9 +37,9 @@ namespace {
 constexpr double kUnit = 1048576.0;
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kTwo30 = 1073741824.0;
-constexpr int kStages = 13;
+constexpr int kStages = 14;
 enum { ST_PARAMS = 0, ST_FFT_A, ST_FFT_B, ST_COUNT, ST_SCAN, ST_SCATTER, ST_SPLAT, ST_PLAN, ST_REDUCE, ST_BINPLAN,
-       ST_DEPX, ST_FILTY, ST_LSUM };
+       ST_DEPX, ST_FILTY, ST_LSUM, ST_NORMALS };
 
 int64_t pmod(int64_t a, int64_t m) {
   int64_t r = a % m;
@@ -210,6 +210,7 @@ int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out) {
   if (!(cfg->fft_L > 0) || !(cfg->g > 0) || !(cfg->dt > 0)) return HWO_EINVAL;
   if (cfg->max_particles < 0 || cfg->max_particles > ((int64_t)1 << 30)) return HWO_EINVAL;
   if (cfg->synth != 0 && cfg->synth != 1) return HWO_EINVAL;
+  if (cfg->normals != 0 && cfg->normals != 1) return HWO_EINVAL;
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return HWO_EINVAL;
   hwo_ocean *o = new hwo_ocean();
   o->cfg = *cfg;
@@ -680,6 +681,12 @@ static int finalize(hwo_ocean *o) {
   d.H = (float *)o->alloc(sizeof(float) * (size_t)N * N);
   d.raw = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
+  d.ncells = cells;
+  if (o->cfg.normals) {
+    d.nrm = (float *)o->alloc(sizeof(float) * 3 * (size_t)std::max<int64_t>(cells, 1));
+    if (!d.nrm) return o->fail(HWO_ENOMEM, "device allocation failed");
+    HWO_CHECK(hipMemsetAsync(d.nrm, 0, sizeof(float) * 3 * (size_t)std::max<int64_t>(cells, 1), o->st));
+  }
   // splat work plan
   d.max_items = d.ntiles + 8192;
   d.chunk_load = 2500;   // least estimated cost per work item (a few hundred particle visits)
@@ -727,7 +734,6 @@ static int finalize(hwo_ocean *o) {
   d.synth = o->cfg.synth;
   if (d.synth == 1 && np > 0) {
     d.n_xtiles = o->xt_base.back();
-    d.ncells = cells;
     // trough offsets round(r (cos, sin) 2^20): the texel a trough lands in is an integer decision
     o->toff.resize((size_t)nb * kNCode);
     for (int b = 0; b < nb; ++b)
@@ -823,6 +829,7 @@ static void launch_stage(hwo_ocean *o, int stage, const PatchArg *g) {
     case ST_DEPX: launch_deposit_x(d, nullptr, 0, o->st); break;
     case ST_FILTY: launch_filter_y(d, 0, d.ntiles, o->st); break;
     case ST_LSUM: launch_layer_sum(d, 0, d.np, d.ncells, d.raw, d.blend, 0, o->st); break;
+    case ST_NORMALS: launch_normals(d, o->st); break;
     default: break;
   }
 }
@@ -918,6 +925,7 @@ static void run_step(hwo_ocean *o) {
         timed(o, ST_REDUCE, &gp);
       }
     }
+    if (o->cfg.normals) timed(o, ST_NORMALS, nullptr);
   }
   join();
 }
@@ -991,9 +999,10 @@ int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst, 
     n = (int64_t)d.N * d.N;
   } else {
     if (which < 0 || which >= d.np) return o->fail(HWO_ERANGE, "patch out of range");
-    if (layer != 0 && layer != 1) return o->fail(HWO_EINVAL, "layer must be 0 or 1");
+    if (layer < 0 || layer > 4) return o->fail(HWO_EINVAL, "layer must be 0..4");
+    if (layer >= 2 && !d.nrm) return o->fail(HWO_ESTATE, "normals are not enabled (hwo_config.normals)");
     const PatchDev &P = o->pdev[which];
-    src = (layer == 0 ? d.blend : d.raw) + P.cell0;
+    src = (layer == 0 ? d.blend : layer == 1 ? d.raw : d.nrm + (size_t)(layer - 2) * d.ncells) + P.cell0;
     n = (int64_t)P.nx * P.ny;
   }
   if (dst_elems < n) return o->fail(HWO_ERANGE, "destination too small");
@@ -1212,8 +1221,10 @@ int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep
   if (!o || !ms_per_rep || reps < 1) return HWO_EINVAL;
   const bool splat_stage = stage == ST_PLAN || stage == ST_SPLAT || stage == ST_REDUCE;
   const bool layer_stage = stage == ST_DEPX || stage == ST_FILTY || stage == ST_LSUM;
-  if (stage != ST_FFT_A && stage != ST_FFT_B && !splat_stage && !layer_stage)
+  const bool normal_stage = stage == ST_NORMALS;
+  if (stage != ST_FFT_A && stage != ST_FFT_B && !splat_stage && !layer_stage && !normal_stage)
     return o->fail(HWO_EINVAL, "stage is not repeatable (it advances or consumes state)");
+  if (normal_stage && !o->cfg.normals) return o->fail(HWO_EINVAL, "normals are not enabled");
   if ((splat_stage && o->cfg.synth == 1) || (layer_stage && o->cfg.synth != 1))
     return o->fail(HWO_EINVAL, "stage is not part of this synthesis mode");
   if (o->n_host < 1) return o->fail(HWO_ESTATE, "time_stage needs a completed step");
@@ -1225,7 +1236,7 @@ int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep
   HWO_CHECK(hipEventCreate(&b));
   HWO_CHECK(hipEventRecord(a, o->st));
   for (int k = 0; k < reps; ++k) {
-    if (stage == ST_FFT_A || stage == ST_FFT_B || layer_stage) launch_stage(o, stage, nullptr);
+    if (stage == ST_FFT_A || stage == ST_FFT_B || layer_stage || normal_stage) launch_stage(o, stage, nullptr);
     else
       for (const auto &gp : groups) launch_stage(o, stage, &gp);
   }

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "_build", "libhwo.so")
 
 HWO_OK, HWO_EINVAL, HWO_ESTATE, HWO_ENOMEM, HWO_EDEVICE, HWO_ERANGE, HWO_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
 STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "splat_plan", "splat_reduce",
-          "bin_plan", "deposit_x", "filter_y", "layer_sum"]
+          "bin_plan", "deposit_x", "filter_y", "layer_sum", "normals"]
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
@@ -31,7 +31,7 @@ class HwoConfig(C.Structure):
     _fields_ = [("fft_n", C.c_int32), ("fft_L", C.c_double), ("g", C.c_double), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("compact", C.c_int32), ("batched", C.c_int32), ("stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("max_particles", C.c_int64), ("synth", C.c_int32)]
+                ("max_particles", C.c_int64), ("synth", C.c_int32), ("normals", C.c_int32)]
 
 
 class HwoSpectrum(C.Structure):
@@ -136,7 +136,7 @@ class Ocean:
     """One hybrid ocean on the GPU, built from a :class:`scenes.Scene`."""
 
     def __init__(self, scene, *, compact=None, batched=None, bins=None, max_particles=0,
-                 torch_memory=True, stream=None):
+                 torch_memory=True, stream=None, normals=False):
         self.L = lib()
         self.scene = scene
         self.h = C.c_void_p()
@@ -162,6 +162,7 @@ class Ocean:
             cfg.dev_free = self._alloc.free_cb
         cfg.max_particles = int(max_particles)
         cfg.synth = int(getattr(scene, "synth", 0))
+        cfg.normals = int(bool(normals))
         self._cfg = cfg
         self._check(self.L.hwo_create_ocean(C.byref(cfg), C.byref(self.h)))
         sp = scene.spectrum
@@ -222,6 +223,10 @@ class Ocean:
         out = np.zeros((pt.ny, pt.nx), dtype=np.float32)
         self._check(self.L.hwo_read_heightmaps(self.h, p, layer, out.ctypes.data, out.size, 0))
         return out
+
+    def normals(self, p: int) -> np.ndarray:
+        """Unit normals (3, ny, nx) of patch p's blended map (needs normals=True)."""
+        return np.stack([self.patch_map(p, layer) for layer in (2, 3, 4)])
 
     def read_into(self, which: int, layer: int, tensor):
         """Device-to-device copy of a height map into a CUDA tensor (float32)."""

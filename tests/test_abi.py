@@ -61,7 +61,7 @@ def test_create_validates_config(L):
     h = C.c_void_p()
     assert L.hwo_create_ocean(None, C.byref(h)) == hwo.HWO_EINVAL
     for bad in (dict(fft_n=100), dict(fft_n=8), dict(fft_n=8192), dict(fft_L=0.0), dict(g=-1.0),
-                dict(dt=0.0), dict(max_particles=-5), dict(synth=2)):
+                dict(dt=0.0), dict(max_particles=-5), dict(synth=2), dict(normals=3)):
         assert L.hwo_create_ocean(C.byref(cfg(**bad)), C.byref(h)) == hwo.HWO_EINVAL, bad
     assert L.hwo_create_ocean(C.byref(cfg()), C.byref(h)) == hwo.HWO_OK
     assert h.value
@@ -87,7 +87,7 @@ def test_call_order_errors(L):
     assert L.hwo_read_buckets(h, buf, 64) == hwo.HWO_ESTATE   # before set_spectrum
     ms = C.c_double()
     # only idempotent stages can be re-launched, and only after a step
-    for stage in (0, 3, 4, 5, 13):   # params, count, scan, scatter, no such stage
+    for stage in (0, 3, 4, 5, 13, 14):   # params, count, scan, scatter, normals (off), no such stage
         assert L.hwo_time_stage(h, stage, 5, C.byref(ms)) == hwo.HWO_EINVAL
     for stage in (10, 11, 12):   # layer stages need synth 1
         assert L.hwo_time_stage(h, stage, 5, C.byref(ms)) == hwo.HWO_EINVAL

@@ -392,6 +392,32 @@ def test_texel_layer_synthesis(name, steps, form):
     say(f"texel layers {name} {form} err={e}")
 
 
+@pytest.mark.parametrize("name,steps,form,synth", [("c1", 20, "plain", 0), ("c2", 60, "batched", 0),
+                                                   ("p0", 40, "batched", 1)])
+def test_finite_difference_normals(name, steps, form, synth):
+    """Normals of the blended maps by finite differences (Sec 4.2), computed
+    on the GPU every frame, against the oracle's normals of its own blended
+    map: x and y components within the height tolerance (relative RMS), z
+    likewise, every normal of unit length."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.get(name).replace(synth=synth)
+    kw = dict(compact=True, batched=True) if form == "batched" else {}
+    say(f"normals {name} {form} synth={synth}")
+    g = hwo.Ocean(s, normals=True, **kw)
+    o = oracle.Oracle(s)
+    g.step(steps)
+    o.step(steps)
+    H = o.background()
+    for p in range(len(s.patches)):
+        _, bl = o.patch_maps(p, H)
+        want = o.normals(p, bl)
+        got = g.normals(p)
+        errs = [rel_rms(got[c], want[c]) for c in range(3)]
+        say(f"normals {name} patch {p} rel rms {errs}")
+        assert max(errs) <= TOL
+        assert np.max(np.abs(np.sum(got.astype(np.float64) ** 2, axis=0) - 1.0)) <= 1e-5
+
+
 # ---------------------------------------------------------------- edge cases
 def test_capacity_overflow_reported():
     """More live particles than capacity: records beyond it are dropped,

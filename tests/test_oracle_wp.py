@@ -576,3 +576,40 @@ def test_texel_layers_sum_buckets_and_blend():
     assert np.array_equal(o0.particles(), P)
     raw0, _ = o0.patch_maps(0)
     assert np.sqrt(np.mean((raw - raw0) ** 2)) < 0.05 * np.sqrt(np.mean(raw0 ** 2))
+
+
+# ---------------------------------------------------------------- normals
+def test_normals_exact_for_planes_and_closed_form_for_cosines():
+    """Sec 4.2 normals by finite differences.  Central (and the one-sided
+    edge) differences are exact for a plane h = a x + b y, giving the normal
+    (-a, -b, 1) / sqrt(1 + a^2 + b^2) everywhere.  For h = A cos(k x) the
+    interior central difference is -A sin(k x) sin(k dx) / dx exactly, which
+    tends to the analytic slope -A k sin(k x) as dx^2."""
+    s = pin_scene(nx=64, dx=0.25)
+    o = oracle.Oracle(s)
+    p = s.patches[0]
+    xc = (np.arange(p.nx) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, xc)
+    a, b = 0.3, -0.7
+    n = o.normals(0, a * X + b * Y)
+    want = np.array([-a, -b, 1.0]) / math.sqrt(1 + a * a + b * b)
+    assert np.max(np.abs(n - want[:, None, None])) <= 1e-12
+    A, k = 0.4, 2 * math.pi / 3.0
+    n = o.normals(0, A * np.cos(k * X))
+    sx = -A * np.sin(k * X[:, 1:-1]) * math.sin(k * p.dx) / p.dx
+    inv = 1.0 / np.sqrt(1 + sx * sx)
+    assert np.max(np.abs(n[0][:, 1:-1] - (-sx * inv))) <= 1e-12
+    assert np.max(np.abs(n[2][:, 1:-1] - inv)) <= 1e-12
+    assert np.max(np.abs(n[1])) <= 1e-12
+    assert np.allclose(np.sum(n * n, axis=0), 1.0, atol=1e-12)
+    # second order: the gap to the analytic normal falls by 4 when dx halves
+    errs = []
+    for nx, dx in ((64, 0.25), (128, 0.125)):
+        s2 = pin_scene(nx=nx, dx=dx)
+        o2 = oracle.Oracle(s2)
+        xc = (np.arange(nx) + 0.5) * dx
+        X2, _ = np.meshgrid(xc, xc)
+        n2 = o2.normals(0, A * np.cos(k * X2))
+        ex = A * k * np.sin(k * X2)   # -dh/dx
+        errs.append(np.max(np.abs(n2[0][:, 1:-1] - ex[:, 1:-1] / np.sqrt(1 + ex[:, 1:-1] ** 2))))
+    assert 3.5 < errs[0] / errs[1] < 4.5
