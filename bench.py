@@ -348,7 +348,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        nf = args.cpu_frames or (10 if args.config in ("c1", "c2", "c4") else 1)
+        nf = args.cpu_frames or (200 if args.config in ("c1", "c2", "c4") else 1)
         cms, csec = cpu_baseline(scene, preroll + W, nf)
         cpu = {"value": round(cms, 3), "unit": "ms/frame", "cores": 1, "kind": "oracle",
                "sample": f"{nf} full frames (bookkeeping, FP64 FFT background, splat and blend of every "
