@@ -376,7 +376,8 @@ def test_gpu_texel_layers_random_particles(compact):
 
 
 @pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "plain"),
-                                             ("c2", 60, "batched"), ("p0", 40, "batched")])
+                                             ("c2", 60, "batched"), ("p0", 40, "batched"),
+                                             ("c3", 12, "batched"), ("c3", 12, "plain")])
 def test_texel_layer_synthesis(name, steps, form):
     """Scenes through the texel layers (deposit, x pass, y pass, layer sum,
     blend): integer state bit-exact and heights against the oracle's layer
@@ -393,7 +394,7 @@ def test_texel_layer_synthesis(name, steps, form):
 
 
 @pytest.mark.parametrize("name,steps,form,synth", [("c1", 20, "plain", 0), ("c2", 60, "batched", 0),
-                                                   ("p0", 40, "batched", 1)])
+                                                   ("p0", 40, "batched", 1), ("c3", 12, "batched", 0)])
 def test_finite_difference_normals(name, steps, form, synth):
     """Normals of the blended maps by finite differences (Sec 4.2), computed
     on the GPU every frame, against the oracle's normals of its own blended
