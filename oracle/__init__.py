@@ -59,6 +59,7 @@ def lib():
         "orc_set_bins": (C.c_int, [vp, P(i32)]),
         "orc_set_synthesis": (C.c_int, [vp, i32]),
         "orc_normals": (C.c_int, [vp, i32, P(dbl), P(dbl)]),
+        "orc_background_field": (C.c_int, [vp, i32, dbl, P(dbl)]),
         "orc_step": (C.c_int, [vp, i32]),
         "orc_step_index": (i64, [vp]),
         "orc_background": (C.c_int, [vp, P(dbl)]),
@@ -203,6 +204,14 @@ class Oracle:
         else:
             self._check(self.L.orc_background_at(self.h, float(t), _p(H, C.c_double)))
         return H
+
+    def background_field(self, field: int, t=None) -> np.ndarray:
+        """Background field (N, N): 0 height, 1 dH/dx, 2 dH/dy, 3/4 choppy displacement x/y."""
+        N = self.scene.fft_n
+        out = np.zeros((N, N), dtype=np.float64)
+        tt = self.n * self.scene.dt if t is None else float(t)
+        self._check(self.L.orc_background_field(self.h, int(field), tt, _p(out, C.c_double)))
+        return out
 
     def patch_maps(self, p: int, H=None, blended=True):
         pt = self.scene.patches[p]

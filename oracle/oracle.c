@@ -950,8 +950,15 @@ int orc_set_h0(orc_ocean *o, const double *re, const double *im) {
 
 /* H(x_j, t) = Re sum_k htilde(k, t) e^{i k.x_j},
  * htilde(k, t) = h0(k) e^{-i w t} + conj(h0(-k)) e^{+i w t}, w = sqrt(g |k|). */
-int orc_background_at(orc_ocean *o, double t, double *H) {
+/* Background fields derived from the same spectrum (choppy displacement and
+ * slopes, the usual companions of the height transform): field 0 height H,
+ * 1 and 2 the slopes dH/dx and dH/dy (spectrum times i kx, i ky), 3 and 4
+ * the horizontal displacements D = sum -i (k / |k|) h~ e^{ik.x} (x and y).
+ * For fields 1-4 the Nyquist rows and columns and k = 0 carry nothing, so
+ * every field stays real. */
+int orc_background_field(orc_ocean *o, int32_t field, double t, double *H) {
     if (!o->have_spec) return fail(o, "set_spectrum first");
+    if (field < 0 || field > 4) return fail(o, "field must be 0..4");
     int32_t N = o->N;
     size_t n2 = (size_t)N * N;
     double *re = (double *)malloc(sizeof(double) * n2);
@@ -968,8 +975,22 @@ int orc_background_at(orc_ocean *o, double t, double *H) {
             double ar = o->h0re[a], ai = o->h0im[a];
             double br = o->h0re[b], bi = -o->h0im[b]; /* conj(h0(-k)) */
             /* a e^{-iwt} + b e^{+iwt} */
-            re[a] = ar * c + ai * s + br * c - bi * s;
-            im[a] = ai * c - ar * s + bi * c + br * s;
+            double hr = ar * c + ai * s + br * c - bi * s;
+            double hi = ai * c - ar * s + bi * c + br * s;
+            double m = 0.0; /* the factor is i m for fields 1-4 */
+            if (field != 0 && jx != N / 2 && jy != N / 2) {
+                double kk = sqrt(kx * kx + ky * ky);
+                if (field == 1) m = kx;
+                else if (field == 2) m = ky;
+                else if (kk > 0.0) m = -(field == 3 ? kx : ky) / kk;
+            }
+            if (field == 0) {
+                re[a] = hr;
+                im[a] = hi;
+            } else {
+                re[a] = -m * hi;
+                im[a] = m * hr;
+            }
         }
     orc_fft2_inverse(re, im, N);
     for (size_t k = 0; k < n2; ++k) H[k] = re[k];
@@ -977,6 +998,8 @@ int orc_background_at(orc_ocean *o, double t, double *H) {
     free(im);
     return 0;
 }
+
+int orc_background_at(orc_ocean *o, double t, double *H) { return orc_background_field(o, 0, t, H); }
 
 int orc_background(orc_ocean *o, double *H) { return orc_background_at(o, (double)o->n * o->dt, H); }
 

@@ -43,6 +43,10 @@ int orc_set_synthesis(orc_ocean *o, int32_t mode);
 /* Unit normals of patch p from height map h (ny x nx) by finite differences
  * (Sec 4.2); out holds three ny x nx planes: x, y and z components. */
 int orc_normals(orc_ocean *o, int32_t p, const double *h, double *out);
+/* Background field at time t (N x N, row-major [y][x]): 0 height, 1 dH/dx,
+ * 2 dH/dy, 3 and 4 the choppy displacement sum -i (k/|k|) h~ e^{ik.x}
+ * (x and y); fields 1-4 exclude the Nyquist rows/columns. */
+int orc_background_field(orc_ocean *o, int32_t field, double t, double *H);
 int orc_step(orc_ocean *o, int32_t nsteps);
 int64_t orc_step_index(const orc_ocean *o);
 

@@ -113,3 +113,55 @@ def test_background_variance_matches_spectrum():
     assert ratio.size > 4000
     assert ratio.mean() == pytest.approx(1.0, abs=4.0 / math.sqrt(ratio.size))
     assert ratio.var() == pytest.approx(1.0, abs=0.15)
+
+
+@pytest.mark.parametrize("mode", [(3, 0), (0, 5), (-4, 7), (11, -2)])
+def test_slope_and_choppy_fields_of_a_single_mode(mode):
+    """Derived background fields of one spectral mode h0(k0) = a e^{i phi},
+    H = 2a cos(theta) with theta = k0.x - w t + phi: the slopes are the exact
+    derivatives -2a k0x sin(theta), -2a k0y sin(theta), and the choppy
+    displacement sum -i (k/|k|) h~ e^{ik.x} is (k0 / |k0|) 2a sin(theta)."""
+    s = scenes.c1()
+    o = oracle.Oracle(s)
+    N, L, g = s.fft_n, s.fft_L, s.g
+    mx, my = mode
+    z = np.zeros((N, N), dtype=complex)
+    a, phi = 0.3, 0.7
+    z[my % N, mx % N] = a * np.exp(1j * phi)
+    o.set_h0(z)
+    k0 = 2 * math.pi / L * np.array([mx, my])
+    kn = np.linalg.norm(k0)
+    w = math.sqrt(g * kn)
+    x = np.arange(N) * L / N
+    X, Y = np.meshgrid(x, x)
+    for t in (0.0, 3.25):
+        th = k0[0] * X + k0[1] * Y - w * t + phi
+        want = {1: -2 * a * k0[0] * np.sin(th), 2: -2 * a * k0[1] * np.sin(th),
+                3: 2 * a * k0[0] / kn * np.sin(th), 4: 2 * a * k0[1] / kn * np.sin(th)}
+        for f, v in want.items():
+            assert np.max(np.abs(o.background_field(f, t) - v)) <= 1e-11, (f, t)
+
+
+def test_derived_fields_are_spectral_derivatives_of_the_height():
+    """On a full spectrum the derived fields are the spectral derivative and
+    the Riesz transform of the oracle's own height field: numpy's FFT of H,
+    times i kx, i ky or -i k/|k| (Nyquist rows and columns and k = 0
+    dropped), transformed back, reproduces fields 1-4.  This ties the derived
+    transforms to the height transform through an independent FFT."""
+    s = scenes.c1()
+    s.spectrum.h0_mode = 1
+    o = oracle.Oracle(s)
+    N, L = s.fft_n, s.fft_L
+    t = 1.5
+    Hk = np.fft.fft2(o.background(t))
+    m = np.fft.fftfreq(N, 1.0 / N)
+    KX, KY = np.meshgrid(2 * math.pi / L * m, 2 * math.pi / L * m)
+    keep = (np.abs(np.meshgrid(m, m)[0]) != N // 2) & (np.abs(np.meshgrid(m, m)[1]) != N // 2)
+    kk = np.hypot(KX, KY)
+    inv = np.where(kk > 0, 1.0 / np.where(kk > 0, kk, 1.0), 0.0)
+    mult = {1: 1j * KX, 2: 1j * KY, 3: -1j * KX * inv, 4: -1j * KY * inv}
+    for f, mk in mult.items():
+        want = np.fft.ifft2(Hk * mk * keep)
+        got = o.background_field(f, t)
+        assert np.max(np.abs(want.imag)) <= 1e-12 * np.max(np.abs(want.real))
+        assert np.max(np.abs(got - want.real)) <= 1e-10 * np.max(np.abs(want.real)), f
