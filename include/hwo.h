@@ -76,6 +76,9 @@ typedef struct {
     int32_t normals;        /* 1: also derive unit normals of the blended maps by
                                finite differences every frame (Sec 4.2), read as
                                layers 2-4 of hwo_read_heightmaps; 0: none */
+    int32_t bg_fields;      /* 1: the FFT also makes the background slopes dH/dx,
+                               dH/dy and the choppy displacement (x, y), read as
+                               layers 1-4 of the background; 0: height only */
 } hwo_config;
 
 /* Spectrum and bucket parameters (Sec 3.1, Sec 3.3). */
@@ -147,7 +150,10 @@ int hwo_sync(hwo_ocean *o);
 int64_t hwo_step_index(const hwo_ocean *o);
 
 /* Copy a height map (FP32, row-major [y][x]) into dst (host or device memory
- * per dst_is_device).  which = -1: background N x N; which = p >= 0: patch p
+ * per dst_is_device).  which = -1: background N x N, layer 0 the height,
+ * 1 dH/dx, 2 dH/dy, 3 and 4 the choppy displacement sum -i (k/|k|) h~
+ * e^{ik.x} in x and y (HWO_ESTATE unless hwo_config.bg_fields; these fields
+ * omit the Nyquist rows and columns); which = p >= 0: patch p
  * (ny x nx) with layer 0 = blended, 1 = raw wave-particle height, 2, 3, 4 =
  * x, y, z component of the unit normal of the blended map (central
  * differences, one-sided at the patch edges; HWO_ESTATE unless

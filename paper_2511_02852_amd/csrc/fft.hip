@@ -16,6 +16,12 @@
 //           (Z = F_a + i F_b), write H[jy_a] = Re, H[jy_b] = Im.
 // HBM bytes per point: h0 8 (read) + F 4 (write) + F 4 (read) + H 4 (write).
 // h0 and the twiddles are generated in FP64 and stored FP32.
+//
+// Optional derived fields (blockIdx.y = field, one launch per pass for all):
+// the slopes dH/dx, dH/dy (spectrum times i kx, i ky) and the choppy
+// displacement sum -i (k/|k|) h~ e^{ik.x}; each is real, so the same two
+// passes apply.  Their Nyquist rows and columns and k = 0 are dropped (an
+// odd multiplier would make the Nyquist terms non-Hermitian).
 #include "hwo_dev.h"
 
 namespace hwo {
@@ -143,6 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
   __shared__ float2 buf[F * N];
   const int f = threadIdx.x / T, t = threadIdx.x % T;
   const int mx = blockIdx.x * F + f;
+  const int field = blockIdx.y;
   const bool active = mx <= N / 2;
   const float tn = (float)((double)d.glob->n * d.dt);
   const float dk = (float)(2.0 * M_PI / d.L);
@@ -175,6 +182,20 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
       // a e^{-iwt} + conj(b) e^{+iwt}
       float re = fmaf(a.x + b.x, c, (a.y + b.y) * s);
       float im = fmaf(a.y - b.y, c, (b.x - a.x) * s);
+      if (field != 0) {   // times i m
+        float m = 0.f;
+        if (mx != N / 2 && e != N / 2) {
+          if (field == 1) m = kx;
+          else if (field == 2) m = ky;
+          else {
+            const float kk2 = fmaf(kx, kx, ky * ky);
+            m = kk2 > 0.f ? -(field == 3 ? kx : ky) * rsqrtf(kk2) : 0.f;
+          }
+        }
+        const float r2 = -m * im;
+        im = m * re;
+        re = r2;
+      }
       row[e] = make_float2(re, im);
     }
   } else {
@@ -183,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
   __syncthreads();
   fft_lds<N, T>(row, t, d.tw);
   if (active) {
-    float2 *__restrict__ out = d.FT + (size_t)mx * N;
+    float2 *__restrict__ out = d.FT + (size_t)field * (N / 2 + 1) * N + (size_t)mx * N;
     for (int e = t; e < N; e += T) out[e] = row[e];
   }
 }
@@ -204,6 +225,7 @@ __global__ __launch_bounds__(FftShapeB<N>::B) void k_fft_b(Dev d) {
   __shared__ float2 buf[F * N];
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int jy0 = blk * C;
+  const float2 *__restrict__ FT = d.FT + (size_t)blockIdx.y * (N / 2 + 1) * N;
   // Load the half plane F[0..N/2][jy0 .. jy0+C) with consecutive threads on
   // consecutive column pairs of one row, and rebuild the full x-spectrum:
   // Z[mx] = F_a[mx] + i F_b[mx], Z[N-mx] = conj(F_a[mx]) + i conj(F_b[mx]).
@@ -215,7 +237,7 @@ __global__ __launch_bounds__(FftShapeB<N>::B) void k_fft_b(Dev d) {
     const int q = (int)threadIdx.x + k * B;
     if (q < Q) {
       const int mx = q / F, f = q % F;
-      v[k] = *reinterpret_cast<const float4 *>(d.FT + (size_t)mx * N + jy0 + 2 * f);
+      v[k] = *reinterpret_cast<const float4 *>(FT + (size_t)mx * N + jy0 + 2 * f);
     }
   }
 #pragma unroll
@@ -233,7 +255,7 @@ __global__ __launch_bounds__(FftShapeB<N>::B) void k_fft_b(Dev d) {
   const int f = threadIdx.x / T, t = threadIdx.x % T;
   float2 *row = buf + f * N;
   fft_lds<N, T>(row, t, d.tw);
-  float *__restrict__ ha = d.H + (size_t)(jy0 + 2 * f) * N;
+  float *__restrict__ ha = d.H + (size_t)blockIdx.y * N * N + (size_t)(jy0 + 2 * f) * N;
   float *__restrict__ hb = ha + N;
   for (int e = t; e < N; e += T) {
     float2 z = row[e];
@@ -312,11 +334,11 @@ void launch_h0(const Dev &d, float2 *h0T, float2 *tw, double alpha, double wp, d
 template <int N> static void fft_a_n(const Dev &d, hipStream_t st) {
   constexpr int F = FftShape<N>::F;
   const int rows = N / 2 + 1;
-  hipLaunchKernelGGL(k_fft_a<N>, dim3((rows + F - 1) / F), dim3(kThreads), 0, st, d);
+  hipLaunchKernelGGL(k_fft_a<N>, dim3((rows + F - 1) / F, d.nfields), dim3(kThreads), 0, st, d);
 }
 template <int N> static void fft_b_n(const Dev &d, hipStream_t st) {
   constexpr int F = FftShapeB<N>::F;
-  hipLaunchKernelGGL(k_fft_b<N>, dim3(N / (2 * F)), dim3(FftShapeB<N>::B), 0, st, d);
+  hipLaunchKernelGGL(k_fft_b<N>, dim3(N / (2 * F), d.nfields), dim3(FftShapeB<N>::B), 0, st, d);
 }
 
 void launch_fft_a(const Dev &d, hipStream_t st) {

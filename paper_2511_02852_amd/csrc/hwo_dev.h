@@ -149,8 +149,9 @@ struct Dev {
   void *S0, *S1;               // particle buffers; step n reads S[(n-1)&1], writes S[n&1]
   const float2 *h0T;           // [N][N] h0 transposed: row = kx index
   const float2 *tw;            // [N] e^{2 pi i k / N}
-  float2 *FT;                  // [N/2+1][N]
-  float *H;                    // [N][N]
+  int32_t nfields;             // background fields: 1 height, or 5 (+ dH/dx, dH/dy, choppy Dx, Dy)
+  float2 *FT;                  // [nfields][N/2+1][N]
+  float *H;                    // [nfields][N][N], field 0 the height
   float *raw, *blend;          // heights, all patches
   // splat work plan
   uint32_t *tile_load;         // [ntiles] estimated splat cost per output tile (model units)

@@ -211,6 +211,7 @@ int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out) {
   if (cfg->max_particles < 0 || cfg->max_particles > ((int64_t)1 << 30)) return HWO_EINVAL;
   if (cfg->synth != 0 && cfg->synth != 1) return HWO_EINVAL;
   if (cfg->normals != 0 && cfg->normals != 1) return HWO_EINVAL;
+  if (cfg->bg_fields != 0 && cfg->bg_fields != 1) return HWO_EINVAL;
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return HWO_EINVAL;
   hwo_ocean *o = new hwo_ocean();
   o->cfg = *cfg;
@@ -677,8 +678,9 @@ static int finalize(hwo_ocean *o) {
   d.S1 = o->alloc(rec * (size_t)d.cap);
   d.h0T = o->h0T;
   d.tw = o->tw;
-  d.FT = (float2 *)o->alloc(sizeof(float2) * (size_t)(N / 2 + 1) * N);
-  d.H = (float *)o->alloc(sizeof(float) * (size_t)N * N);
+  d.nfields = o->cfg.bg_fields ? 5 : 1;   // height, or height + slopes + choppy displacements
+  d.FT = (float2 *)o->alloc(sizeof(float2) * (size_t)(N / 2 + 1) * N * d.nfields);
+  d.H = (float *)o->alloc(sizeof(float) * (size_t)N * N * d.nfields);
   d.raw = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   d.blend = (float *)o->alloc(sizeof(float) * (size_t)std::max<int64_t>(cells, 1));
   d.ncells = cells;
@@ -779,7 +781,7 @@ static int finalize(hwo_ocean *o) {
   HWO_CHECK(hipMemsetAsync(d.cur, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.raw, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.blend, 0, sizeof(float) * (size_t)std::max<int64_t>(cells, 1), o->st));
-  HWO_CHECK(hipMemsetAsync(d.H, 0, sizeof(float) * (size_t)N * N, o->st));
+  HWO_CHECK(hipMemsetAsync(d.H, 0, sizeof(float) * (size_t)N * N * d.nfields, o->st));
   HWO_CHECK(hipMemsetAsync(d.tile_load, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.tile_meas, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.tile_model, 0, sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1), o->st));
@@ -995,7 +997,9 @@ int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst, 
   const float *src;
   int64_t n;
   if (which == -1) {
-    src = d.H;
+    if (layer < 0 || layer > 4) return o->fail(HWO_EINVAL, "background layer must be 0..4");
+    if (layer >= d.nfields) return o->fail(HWO_ESTATE, "slope and displacement fields are not enabled (hwo_config.bg_fields)");
+    src = d.H + (size_t)layer * d.N * d.N;
     n = (int64_t)d.N * d.N;
   } else {
     if (which < 0 || which >= d.np) return o->fail(HWO_ERANGE, "patch out of range");

@@ -31,7 +31,8 @@ class HwoConfig(C.Structure):
     _fields_ = [("fft_n", C.c_int32), ("fft_L", C.c_double), ("g", C.c_double), ("dt", C.c_double),
                 ("seed", C.c_uint64), ("compact", C.c_int32), ("batched", C.c_int32), ("stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
-                ("max_particles", C.c_int64), ("synth", C.c_int32), ("normals", C.c_int32)]
+                ("max_particles", C.c_int64), ("synth", C.c_int32), ("normals", C.c_int32),
+                ("bg_fields", C.c_int32)]
 
 
 class HwoSpectrum(C.Structure):
@@ -136,7 +137,7 @@ class Ocean:
     """One hybrid ocean on the GPU, built from a :class:`scenes.Scene`."""
 
     def __init__(self, scene, *, compact=None, batched=None, bins=None, max_particles=0,
-                 torch_memory=True, stream=None, normals=False):
+                 torch_memory=True, stream=None, normals=False, bg_fields=False):
         self.L = lib()
         self.scene = scene
         self.h = C.c_void_p()
@@ -163,6 +164,7 @@ class Ocean:
         cfg.max_particles = int(max_particles)
         cfg.synth = int(getattr(scene, "synth", 0))
         cfg.normals = int(bool(normals))
+        cfg.bg_fields = int(bool(bg_fields))
         self._cfg = cfg
         self._check(self.L.hwo_create_ocean(C.byref(cfg), C.byref(self.h)))
         sp = scene.spectrum
@@ -212,10 +214,11 @@ class Ocean:
         return int(self.L.hwo_step_index(self.h))
 
     # -- outputs
-    def background(self) -> np.ndarray:
+    def background(self, field: int = 0) -> np.ndarray:
+        """Background field: 0 height, 1 dH/dx, 2 dH/dy, 3/4 choppy displacement (needs bg_fields)."""
         N = self.scene.fft_n
         out = np.zeros((N, N), dtype=np.float32)
-        self._check(self.L.hwo_read_heightmaps(self.h, -1, 0, out.ctypes.data, out.size, 0))
+        self._check(self.L.hwo_read_heightmaps(self.h, -1, int(field), out.ctypes.data, out.size, 0))
         return out
 
     def patch_map(self, p: int, layer: int = 0) -> np.ndarray:

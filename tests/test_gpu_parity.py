@@ -94,6 +94,23 @@ def test_background_matches_oracle(N, L):
         assert e <= TOL
 
 
+@pytest.mark.parametrize("N,L", [(16, 64.0), (64, 256.0), (512, 1000.0), (2048, 4000.0), (4096, 8000.0)])
+def test_background_slope_and_choppy_fields(N, L):
+    """The derived background fields (dH/dx, dH/dy, choppy displacement x
+    and y) from the same two FFT passes, against the oracle's fields."""
+    s = scenes.Scene(name="bgf", fft_n=N, fft_L=L, seed=6, spectrum=scenes.Spectrum(U10=12.0))
+    say(f"background fields N={N}")
+    from paper_2511_02852_amd import hwo
+    g, o = hwo.Ocean(s, bg_fields=True), oracle.Oracle(s)
+    g.step(7)
+    o.step(7)
+    assert rel_rms(g.background(0), o.background()) <= TOL
+    for f in (1, 2, 3, 4):
+        e = rel_rms(g.background(f), o.background_field(f))
+        say(f"  field {f} rel_rms={e:.3e}")
+        assert e <= TOL
+
+
 def test_background_unit_modulus_and_mitsuyasu():
     sp = scenes.Spectrum(U10=7.0, fetch=30e3, gamma=-1.0, spread_s=-1.0, h0_mode=1, wind_dir=0.6)
     s = scenes.Scene(name="bg2", fft_n=256, fft_L=300.0, seed=9, spectrum=sp)
