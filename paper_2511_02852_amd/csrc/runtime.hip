@@ -855,6 +855,7 @@ static void timed(hwo_ocean *o, int stage, const PatchArg *g) {
 static std::vector<PatchArg> launch_groups(const hwo_ocean *o) {
   const Dev &d = o->dev;
   std::vector<PatchArg> groups;
+  if (d.np == 0) return groups;   // no patches: no particle or splat launches
   if (o->cfg.batched) {
     groups.push_back({0, d.np, 0, d.nbins, true, true, 0, 0});
   } else {

@@ -467,6 +467,14 @@ def test_empty_scene_and_zero_steps():
     o = oracle.Oracle(s)
     o.step(3)
     assert rel_rms(g.background(), o.background()) <= TOL
+    # batched form without patches: the graph, stage timing and the derived
+    # background fields still work (no particle or splat launch is made)
+    gb = hwo.Ocean(s, compact=True, batched=True, bg_fields=True)
+    gb.step(3)
+    for stage in ("fft_a", "fft_b", "splat", "splat_plan", "splat_reduce"):
+        assert gb.time_stage(stage, 2) >= 0.0
+    assert rel_rms(gb.background(), o.background()) <= TOL
+    assert rel_rms(gb.background(3), o.background_field(3)) <= TOL
 
 
 def test_static_source_outside_patch_emits_dead_particles():
