@@ -190,6 +190,16 @@ int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_
 int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, float *dst,
                    int64_t dst_elems);
 
+/* Object-receives-water sampling (Sec 4.3): height and unit normal of the
+ * current frame at n world points.  xy holds n (x, y) pairs in metres (FP64),
+ * out receives n x 4 floats: height, normal x, y, z.  Both in host memory, or
+ * both in device memory when on_device != 0.  A point inside the cell-centre
+ * hull of a patch (the first such patch) samples its blended map, else the
+ * periodic background; bilinear height, slopes from central differences
+ * (one-sided at patch edges) interpolated the same way.  HWO_ESTATE before
+ * the first step; n at most 2^24.  Syncs. */
+int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int32_t on_device);
+
 /* Per-stage timing (benchmark support).  enable != 0 brackets every kernel
  * launch with HIP events (graph replay is then disabled); hwo_stage_times
  * returns accumulated milliseconds and launch counts per stage:

@@ -60,6 +60,7 @@ def lib():
         "orc_set_synthesis": (C.c_int, [vp, i32]),
         "orc_normals": (C.c_int, [vp, i32, P(dbl), P(dbl)]),
         "orc_background_field": (C.c_int, [vp, i32, dbl, P(dbl)]),
+        "orc_sample_probes": (C.c_int, [vp, P(dbl), P(dbl), P(dbl), i64, P(dbl)]),
         "orc_step": (C.c_int, [vp, i32]),
         "orc_step_index": (i64, [vp]),
         "orc_background": (C.c_int, [vp, P(dbl)]),
@@ -211,6 +212,21 @@ class Oracle:
         out = np.zeros((N, N), dtype=np.float64)
         tt = self.n * self.scene.dt if t is None else float(t)
         self._check(self.L.orc_background_field(self.h, int(field), tt, _p(out, C.c_double)))
+        return out
+
+    def sample_probes(self, xy, H=None, blended=None) -> np.ndarray:
+        """Height and unit normal (n, 4) at world points xy (n, 2) from the
+        background H and the patches' blended maps (own maps when None)."""
+        if H is None:
+            H = self.background()
+        if blended is None:
+            blended = [self.patch_maps(p, H)[1] for p in range(len(self.scene.patches))]
+        B = np.ascontiguousarray(np.concatenate([np.ravel(b) for b in blended]) if blended else np.zeros(1))
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        out = np.zeros((xy.shape[0], 4))
+        self._check(self.L.orc_sample_probes(self.h, _p(H, C.c_double), _p(B, C.c_double), _p(xy, C.c_double),
+                                             xy.shape[0], _p(out, C.c_double)))
         return out
 
     def patch_maps(self, p: int, H=None, blended=True):

@@ -1256,6 +1256,102 @@ int orc_normals(orc_ocean *o, int32_t p, const double *h, double *out) {
     return 0;
 }
 
+/* Sec 4.3 object-receives-water: the surface seen by a floating object at
+ * probe points.  A probe inside the cell-centre hull of a patch (the first
+ * such patch in index order) samples that patch's blended map, else the
+ * background (periodic).  Height is the bilinear interpolant of the map;
+ * the slopes are central differences at the four surrounding grid points
+ * (one-sided at a patch's first and last row or column), interpolated the
+ * same way; the normal is (-sx, -sy, 1) normalised.  H is the N x N
+ * background, B the blended maps of all patches back to back; out receives
+ * four values per probe: height and the normal's x, y, z. */
+static void fd_slopes(const double *h, int64_t nx, int64_t ny, int periodic, int64_t i, int64_t j,
+                      double dx, double *sx, double *sy) {
+    int64_t a, b;
+    if (periodic) {
+        a = (i + nx - 1) % nx; b = (i + 1) % nx;
+        *sx = (h[j * nx + b] - h[j * nx + a]) / (2.0 * dx);
+        a = (j + ny - 1) % ny; b = (j + 1) % ny;
+        *sy = (h[b * nx + i] - h[a * nx + i]) / (2.0 * dx);
+        return;
+    }
+    *sx = 0.0;
+    *sy = 0.0;
+    if (nx > 1) {
+        a = i > 0 ? i - 1 : i; b = i < nx - 1 ? i + 1 : i;
+        *sx = (h[j * nx + b] - h[j * nx + a]) / ((double)(b - a) * dx);
+    }
+    if (ny > 1) {
+        a = j > 0 ? j - 1 : j; b = j < ny - 1 ? j + 1 : j;
+        *sy = (h[b * nx + i] - h[a * nx + i]) / ((double)(b - a) * dx);
+    }
+}
+
+int orc_sample_probes(orc_ocean *o, const double *H, const double *B, const double *xy, int64_t n, double *out) {
+    if (!H || !B || (!xy && n > 0) || (!out && n > 0)) return fail(o, "null input");
+    const int64_t N = o->N;
+    const double dxf = o->L / (double)N;
+    for (int64_t q = 0; q < n; ++q) {
+        const double x = xy[2 * q], y = xy[2 * q + 1];
+        const double *h = H;
+        int64_t nx = N, ny = N, i0, j0;
+        double fx, fy, dx = dxf;
+        int periodic = 1;
+        int64_t off = 0;
+        int found = 0;
+        for (int p = 0; p < o->np && !found; ++p) {
+            const patch_t *pt = &o->pt[p];
+            double u = (x - pt->ax) * UNIT / (double)pt->dxu - (double)pt->wx - 0.5;
+            double v = (y - pt->ay) * UNIT / (double)pt->dxu - (double)pt->wy - 0.5;
+            if (u >= 0.0 && v >= 0.0 && u <= (double)(pt->nx - 1) && v <= (double)(pt->ny - 1)) {
+                found = 1;
+                h = B + off;
+                nx = pt->nx;
+                ny = pt->ny;
+                dx = pt->dx;
+                periodic = 0;
+                i0 = (int64_t)floor(u);
+                j0 = (int64_t)floor(v);
+                if (i0 > nx - 2) i0 = nx > 1 ? nx - 2 : 0;
+                if (j0 > ny - 2) j0 = ny > 1 ? ny - 2 : 0;
+                fx = u - (double)i0;
+                fy = v - (double)j0;
+            }
+            off += (int64_t)pt->nx * pt->ny;
+        }
+        if (!found) {
+            double u = x / dxf, v = y / dxf;
+            double fu = floor(u), fv = floor(v);
+            fx = u - fu;
+            fy = v - fv;
+            i0 = pmod((int64_t)fu, N);
+            j0 = pmod((int64_t)fv, N);
+        }
+        double hv = 0.0, sxv = 0.0, syv = 0.0;
+        for (int dj = 0; dj < 2; ++dj)
+            for (int di = 0; di < 2; ++di) {
+                int64_t i = i0 + di, j = j0 + dj;
+                if (periodic) { i %= nx; j %= ny; }
+                else {
+                    if (i > nx - 1) i = nx - 1;
+                    if (j > ny - 1) j = ny - 1;
+                }
+                double w = (di ? fx : 1.0 - fx) * (dj ? fy : 1.0 - fy);
+                double sx, sy;
+                fd_slopes(h, nx, ny, periodic, i, j, dx, &sx, &sy);
+                hv += w * h[j * nx + i];
+                sxv += w * sx;
+                syv += w * sy;
+            }
+        double inv = 1.0 / sqrt(1.0 + sxv * sxv + syv * syv);
+        out[4 * q + 0] = hv;
+        out[4 * q + 1] = -sxv * inv;
+        out[4 * q + 2] = -syv * inv;
+        out[4 * q + 3] = inv;
+    }
+    return 0;
+}
+
 /* Splat caller-placed particles (canonical records) into a patch map at the
  * current step; used by the closed-form pins. */
 int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *raw) {

@@ -47,6 +47,10 @@ int orc_normals(orc_ocean *o, int32_t p, const double *h, double *out);
  * 2 dH/dy, 3 and 4 the choppy displacement sum -i (k/|k|) h~ e^{ik.x}
  * (x and y); fields 1-4 exclude the Nyquist rows/columns. */
 int orc_background_field(orc_ocean *o, int32_t field, double t, double *H);
+/* Height and unit normal at n world points (xy: x, y pairs) from background H
+ * (N x N) and the blended maps B of all patches back to back (Sec 4.3
+ * object-receives-water sampling); out: 4 values per probe (h, nx, ny, nz). */
+int orc_sample_probes(orc_ocean *o, const double *H, const double *B, const double *xy, int64_t n, double *out);
 int orc_step(orc_ocean *o, int32_t nsteps);
 int64_t orc_step_index(const orc_ocean *o);
 

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT, "libhwo.so")
-SOURCES = ["runtime.hip", "fft.hip", "particles.hip", "splat.hip", "layers.hip"]
+SOURCES = ["runtime.hip", "fft.hip", "particles.hip", "splat.hip", "layers.hip", "probes.hip"]
 ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

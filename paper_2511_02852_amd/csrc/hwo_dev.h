@@ -353,6 +353,8 @@ void launch_layer_sum(const Dev &d, int p0, int p1, int64_t cells, float *raw, f
                       hipStream_t st);
 // Finite-difference normals of the blended maps.
 void launch_normals(const Dev &d, hipStream_t st);
+// Height and unit normal at n world points (double2 in, float4 out, device).
+void launch_probes(const Dev &d, const void *xy, int n, void *out, hipStream_t st);
 int scan_blocks(int nbins);
 
 }  // namespace hwo

@@ -1199,6 +1199,38 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
   return HWO_OK;
 }
 
+int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int32_t on_device) {
+  if (!o || n < 0 || n > (1 << 24) || (n > 0 && (!xy || !out))) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  if (o->n_host == 0) return o->fail(HWO_ESTATE, "step at least once before sampling");
+  if (n == 0) return HWO_OK;
+  const Dev &d = o->dev;
+  const void *dxy = xy;
+  void *dout = out;
+  void *txy = nullptr, *tout = nullptr;
+  hipError_t e = hipSuccess;
+  if (!on_device) {
+    e = hipMalloc(&txy, sizeof(double) * 2 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&tout, sizeof(float) * 4 * (size_t)n);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(txy, xy, sizeof(double) * 2 * (size_t)n, hipMemcpyHostToDevice, o->st);
+    dxy = txy;
+    dout = tout;
+  }
+  if (e == hipSuccess) {
+    launch_probes(d, dxy, (int)n, dout, o->st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && !on_device)
+    e = hipMemcpyAsync(out, tout, sizeof(float) * 4 * (size_t)n, hipMemcpyDeviceToHost, o->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(o->st);
+  if (txy) (void)hipFree(txy);
+  if (tout) (void)hipFree(tout);
+  if (e != hipSuccess) return o->hip_fail(e, "sample_probes");
+  return HWO_OK;
+}
+
 int hwo_set_timing(hwo_ocean *o, int32_t enable) {
   if (!o) return HWO_EINVAL;
   int rc = collect_timing(o);

@@ -21,7 +21,7 @@ STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "spla
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
-           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes"]
+           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -97,6 +97,7 @@ def lib():
         "hwo_stage_times": (C.c_int, [vp, P(C.c_double), P(i64), i32]),
         "hwo_time_stage": (C.c_int, [vp, i32, i32, P(C.c_double)]),
         "hwo_record_bytes": (i32, [vp]),
+        "hwo_sample_probes": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -230,6 +231,13 @@ class Ocean:
     def normals(self, p: int) -> np.ndarray:
         """Unit normals (3, ny, nx) of patch p's blended map (needs normals=True)."""
         return np.stack([self.patch_map(p, layer) for layer in (2, 3, 4)])
+
+    def sample_probes(self, xy) -> np.ndarray:
+        """Height and unit normal (n, 4) of the current frame at world points xy (n, 2)."""
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        out = np.zeros((xy.shape[0], 4), dtype=np.float32)
+        self._check(self.L.hwo_sample_probes(self.h, _p(xy, C.c_double), xy.shape[0], _p(out, C.c_float), 0))
+        return out
 
     def read_into(self, which: int, layer: int, tensor):
         """Device-to-device copy of a height map into a CUDA tensor (float32)."""

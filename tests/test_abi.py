@@ -93,6 +93,11 @@ def test_call_order_errors(L):
         assert L.hwo_time_stage(h, stage, 5, C.byref(ms)) == hwo.HWO_EINVAL
     assert L.hwo_time_stage(h, 6, 5, C.byref(ms)) == hwo.HWO_ESTATE
     assert L.hwo_time_stage(h, 6, 0, C.byref(ms)) == hwo.HWO_EINVAL
+    xy = (C.c_double * 4)(0.0, 0.0, 1.0, 1.0)
+    out = (C.c_float * 8)()
+    assert L.hwo_sample_probes(h, xy, -1, out, 0) == hwo.HWO_EINVAL
+    assert L.hwo_sample_probes(h, None, 2, out, 0) == hwo.HWO_EINVAL
+    assert L.hwo_sample_probes(h, xy, 2, out, 0) == hwo.HWO_ESTATE   # no spectrum, no step
     L.hwo_destroy_ocean(h)
     c2 = cfg(compact=1)
     assert L.hwo_create_ocean(C.byref(c2), C.byref(h)) == hwo.HWO_OK

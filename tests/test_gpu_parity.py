@@ -436,6 +436,36 @@ def test_finite_difference_normals(name, steps, form, synth):
         assert np.max(np.abs(np.sum(got.astype(np.float64) ** 2, axis=0) - 1.0)) <= 1e-5
 
 
+@pytest.mark.parametrize("name,steps,form,synth", [("c2", 60, "batched", 0), ("c3", 12, "batched", 0),
+                                                   ("p0", 40, "batched", 1)])
+def test_probe_sampling(name, steps, form, synth):
+    """Object-receives-water sampling at probe points: inside patches (the
+    blended map) and outside (the background), against the oracle sampling
+    its own maps; heights and normals within the height tolerance."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.get(name).replace(synth=synth)
+    g = hwo.Ocean(s, compact=True, batched=True)
+    o = oracle.Oracle(s)
+    g.step(steps)
+    o.step(steps)
+    rng = np.random.default_rng(9)
+    pts = []
+    for p, P in enumerate(s.patches[:4]):
+        wx, wy = o.window(p)
+        x0, y0 = P.anchor_x + wx * P.dx, P.anchor_y + wy * P.dx
+        pts.append(np.column_stack([rng.uniform(x0 - 5, x0 + P.nx * P.dx + 5, 200),
+                                    rng.uniform(y0 - 5, y0 + P.ny * P.dx + 5, 200)]))
+    pts.append(rng.uniform(0, s.fft_L, (200, 2)))
+    pts = np.concatenate(pts)
+    say(f"probes {name}: {pts.shape[0]} points")
+    got = g.sample_probes(pts)
+    want = o.sample_probes(pts)
+    for c in range(4):
+        e = rel_rms(got[:, c], want[:, c])
+        say(f"  component {c} rel rms {e:.2e}")
+        assert e <= TOL
+
+
 # ---------------------------------------------------------------- edge cases
 def test_capacity_overflow_reported():
     """More live particles than capacity: records beyond it are dropped,

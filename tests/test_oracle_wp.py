@@ -613,3 +613,45 @@ def test_normals_exact_for_planes_and_closed_form_for_cosines():
         ex = A * k * np.sin(k * X2)   # -dh/dx
         errs.append(np.max(np.abs(n2[0][:, 1:-1] - ex[:, 1:-1] / np.sqrt(1 + ex[:, 1:-1] ** 2))))
     assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+# ---------------------------------------------------------------- probes
+def test_probe_sampling_exact_for_planes_and_grid_points():
+    """Object-receives-water sampling (Sec 4.3): inside a patch the probe
+    reads the bilinear interpolant of the blended map and a normal from
+    interpolated finite-difference slopes, both exact for a plane; outside
+    every patch it reads the periodic background, and at a background grid
+    point it returns the grid value and the central-difference slope, here
+    checked on one Fourier mode against its closed form."""
+    s = pin_scene(nx=64, dx=0.25)
+    o = oracle.Oracle(s)
+    o.step(1)
+    p = s.patches[0]
+    wx, wy = o.window(0)
+    N, L = s.fft_n, s.fft_L
+    dxf = L / N
+    # plane on the patch, background elsewhere
+    xc = p.anchor_x + (wx + np.arange(p.nx) + 0.5) * p.dx
+    yc = p.anchor_y + (wy + np.arange(p.ny) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, yc)
+    a, b, c0 = 0.2, -0.35, 1.5
+    plane = a * X + b * Y + c0
+    k = 2 * math.pi / L * 3
+    gx = np.arange(N) * dxf
+    GX, GY = np.meshgrid(gx, gx)
+    H = np.cos(k * GX)
+    rng = np.random.default_rng(3)
+    inside = np.column_stack([rng.uniform(xc[0], xc[-1], 40), rng.uniform(yc[0], yc[-1], 40)])
+    out = o.sample_probes(inside, H=H, blended=[plane])
+    assert np.max(np.abs(out[:, 0] - (a * inside[:, 0] + b * inside[:, 1] + c0))) <= 1e-12
+    want = np.array([-a, -b, 1.0]) / math.sqrt(1 + a * a + b * b)
+    assert np.max(np.abs(out[:, 1:] - want)) <= 1e-12
+    # grid points of the background away from the patch
+    jx = np.array([40, 41, 50, 63]); jy = np.array([5, 60, 33, 47])
+    pts = np.column_stack([jx * dxf, jy * dxf])
+    assert not np.any((pts[:, 0] >= xc[0]) & (pts[:, 0] <= xc[-1]) & (pts[:, 1] >= yc[0]) & (pts[:, 1] <= yc[-1]))
+    out = o.sample_probes(pts, H=H, blended=[plane])
+    assert np.max(np.abs(out[:, 0] - np.cos(k * jx * dxf))) <= 1e-12
+    sx = -np.sin(k * jx * dxf) * math.sin(k * dxf) / dxf
+    assert np.max(np.abs(out[:, 1] - (-sx / np.sqrt(1 + sx * sx)))) <= 1e-12
+    assert np.max(np.abs(out[:, 2])) <= 1e-12
