@@ -72,7 +72,10 @@ typedef struct {
                                particle's exact position (default); 1 the paper's
                                texel layers (Sec 4.2) -- bilinear deposit per bucket,
                                passes along x and y with the raised cosine at
-                               whole-cell offsets, layers summed */
+                               whole-cell offsets, layers summed.  The passes
+                               stage (2R + 81) x 64 floats in LDS, R = ceil(r/dx) - 1,
+                               so a radius beyond 279 cells is HWO_EINVAL at the
+                               first step */
     int32_t normals;        /* 1: also derive unit normals of the blended maps by
                                finite differences every frame (Sec 4.2), read as
                                layers 2-4 of hwo_read_heightmaps; 0: none */
