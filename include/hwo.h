@@ -203,6 +203,21 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * the first step; n at most 2^24.  Syncs. */
 int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int32_t on_device);
 
+/* Checkpoint and resume.  A snapshot is a host-memory image of the state at
+ * the current step boundary (step index, counters, bin offsets, live particle
+ * records, splat partition feedback) plus a fingerprint of the scene.
+ * hwo_snapshot_size gives its size in bytes (HWO_ESTATE before the first
+ * step); hwo_snapshot writes it into dst (HWO_ERANGE if dst_bytes is too
+ * small); hwo_restore loads an image into a handle built with the same scene,
+ * configuration and record form (HWO_EINVAL otherwise), after which stepping
+ * continues exactly as from the saved step: integer state bit for bit,
+ * heights up to FP32 summation order.  Heights read before the next step are
+ * those the handle held before restoring.  The caller owns both buffers.
+ * All three synchronise the stream. */
+int hwo_snapshot_size(hwo_ocean *o, int64_t *bytes);
+int hwo_snapshot(hwo_ocean *o, void *dst, int64_t dst_bytes);
+int hwo_restore(hwo_ocean *o, const void *src, int64_t src_bytes);
+
 /* Per-stage timing (benchmark support).  enable != 0 brackets every kernel
  * launch with HIP events (graph replay is then disabled); hwo_stage_times
  * returns accumulated milliseconds and launch counts per stage:

@@ -1199,6 +1199,144 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
   return HWO_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- snapshot
+// A step boundary is fully described by the step index, the globals, the
+// per-bucket counters, the bin offsets of the last scan (the next step reads
+// its particles through them), the live particle records and the splat's
+// partition feedback; everything else is rebuilt from the step index or the
+// scene.  The image starts with a header and a fingerprint of the scene.
+namespace {
+constexpr uint64_t kSnapMagic = 0x48574f534e415031ull;   // "HWOSNAP1"
+struct SnapHeader {
+  uint64_t magic;
+  uint64_t scene;              // fingerprint of the scene tables
+  int64_t n_host;
+  int32_t np, nb, nbins, ntiles, cap, compact, n_live, pad;
+};
+
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+  const unsigned char *c = (const unsigned char *)p;
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
+
+uint64_t scene_fingerprint(const hwo_ocean *o) {
+  uint64_t h = 0xcbf29ce484222325ull;
+  const hwo_config &c = o->cfg;
+  h = fnv(h, &c.fft_n, sizeof c.fft_n);
+  h = fnv(h, &c.fft_L, sizeof c.fft_L);
+  h = fnv(h, &c.g, sizeof c.g);
+  h = fnv(h, &c.dt, sizeof c.dt);
+  h = fnv(h, &c.seed, sizeof c.seed);
+  h = fnv(h, &c.compact, sizeof c.compact);
+  h = fnv(h, o->w, sizeof(double) * (size_t)o->nb);
+  h = fnv(h, o->pdev.data(), sizeof(PatchDev) * o->pdev.size());   // value-initialised: no stray padding
+  h = fnv(h, o->sdev.data(), sizeof(SourceDev) * o->sdev.size());
+  return h;
+}
+
+int64_t snapshot_bytes(const Dev &d, int32_t n_live) {
+  return (int64_t)sizeof(SnapHeader) + (int64_t)sizeof(Globals) +
+         (int64_t)sizeof(unsigned long long) * d.np * d.nb * CNT_NUM + (int64_t)sizeof(int32_t) * (d.nbins + 1) +
+         (int64_t)(2 * sizeof(uint32_t) + sizeof(float)) * d.ntiles +
+         (int64_t)(d.compact ? sizeof(RecCompact) : sizeof(RecWide)) * n_live;
+}
+}  // namespace
+
+extern "C" {
+
+int hwo_snapshot_size(hwo_ocean *o, int64_t *bytes) {
+  if (!o || !bytes) return HWO_EINVAL;
+  if (!o->finalized || o->n_host == 0) return o->fail(HWO_ESTATE, "snapshot needs a completed step");
+  Globals g{};
+  HWO_CHECK(hipMemcpyAsync(&g, o->dev.glob, sizeof(Globals), hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  *bytes = snapshot_bytes(o->dev, g.n_live);
+  return HWO_OK;
+}
+
+int hwo_snapshot(hwo_ocean *o, void *dst, int64_t dst_bytes) {
+  if (!o || !dst) return HWO_EINVAL;
+  if (!o->finalized || o->n_host == 0) return o->fail(HWO_ESTATE, "snapshot needs a completed step");
+  int rc = collect_timing(o);
+  if (rc) return rc;
+  const Dev &d = o->dev;
+  Globals g{};
+  HWO_CHECK(hipMemcpyAsync(&g, d.glob, sizeof(Globals), hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  if (dst_bytes < snapshot_bytes(d, g.n_live)) return o->fail(HWO_ERANGE, "snapshot buffer too small");
+  char *p = (char *)dst;
+  SnapHeader hd{kSnapMagic, scene_fingerprint(o), o->n_host, d.np, d.nb, d.nbins, d.ntiles, d.cap, d.compact,
+                g.n_live, 0};
+  memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  memcpy(p, &g, sizeof g);
+  p += sizeof g;
+  const size_t rb = d.compact ? sizeof(RecCompact) : sizeof(RecWide);
+  const void *S = (g.n & 1) ? d.S1 : d.S0;
+  const size_t nctr = sizeof(unsigned long long) * (size_t)d.np * d.nb * CNT_NUM;
+  HWO_CHECK(hipMemcpyAsync(p, d.ctr, nctr, hipMemcpyDeviceToHost, o->st));
+  p += nctr;
+  HWO_CHECK(hipMemcpyAsync(p, d.off, sizeof(int32_t) * ((size_t)d.nbins + 1), hipMemcpyDeviceToHost, o->st));
+  p += sizeof(int32_t) * ((size_t)d.nbins + 1);
+  HWO_CHECK(hipMemcpyAsync(p, d.tile_meas, sizeof(uint32_t) * (size_t)d.ntiles, hipMemcpyDeviceToHost, o->st));
+  p += sizeof(uint32_t) * (size_t)d.ntiles;
+  HWO_CHECK(hipMemcpyAsync(p, d.tile_model, sizeof(uint32_t) * (size_t)d.ntiles, hipMemcpyDeviceToHost, o->st));
+  p += sizeof(uint32_t) * (size_t)d.ntiles;
+  HWO_CHECK(hipMemcpyAsync(p, d.tile_ratio, sizeof(float) * (size_t)d.ntiles, hipMemcpyDeviceToHost, o->st));
+  p += sizeof(float) * (size_t)d.ntiles;
+  if (g.n_live > 0) HWO_CHECK(hipMemcpyAsync(p, S, rb * (size_t)g.n_live, hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  return HWO_OK;
+}
+
+int hwo_restore(hwo_ocean *o, const void *src, int64_t src_bytes) {
+  if (!o || !src || src_bytes < (int64_t)(sizeof(SnapHeader) + sizeof(Globals))) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  rc = collect_timing(o);
+  if (rc) return rc;
+  const Dev &d = o->dev;
+  SnapHeader hd;
+  Globals g;
+  const char *p = (const char *)src;
+  memcpy(&hd, p, sizeof hd);
+  p += sizeof hd;
+  memcpy(&g, p, sizeof g);
+  p += sizeof g;
+  if (hd.magic != kSnapMagic) return o->fail(HWO_EINVAL, "not a snapshot");
+  if (hd.scene != scene_fingerprint(o) || hd.np != d.np || hd.nb != d.nb || hd.nbins != d.nbins ||
+      hd.ntiles != d.ntiles || hd.compact != d.compact)
+    return o->fail(HWO_EINVAL, "snapshot of a different scene or record form");
+  if (hd.n_live < 0 || hd.n_live > d.cap || hd.n_live != g.n_live || g.n != hd.n_host || hd.n_host < 1)
+    return o->fail(HWO_EINVAL, "inconsistent snapshot");
+  if (src_bytes < snapshot_bytes(d, hd.n_live)) return o->fail(HWO_EINVAL, "truncated snapshot");
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  const size_t rb = d.compact ? sizeof(RecCompact) : sizeof(RecWide);
+  void *S = (g.n & 1) ? d.S1 : d.S0;
+  HWO_CHECK(hipMemcpyAsync(d.glob, &g, sizeof g, hipMemcpyHostToDevice, o->st));
+  const size_t nctr = sizeof(unsigned long long) * (size_t)d.np * d.nb * CNT_NUM;
+  HWO_CHECK(hipMemcpyAsync(d.ctr, p, nctr, hipMemcpyHostToDevice, o->st));
+  p += nctr;
+  HWO_CHECK(hipMemcpyAsync(d.off, p, sizeof(int32_t) * ((size_t)d.nbins + 1), hipMemcpyHostToDevice, o->st));
+  p += sizeof(int32_t) * ((size_t)d.nbins + 1);
+  HWO_CHECK(hipMemcpyAsync(d.tile_meas, p, sizeof(uint32_t) * (size_t)d.ntiles, hipMemcpyHostToDevice, o->st));
+  p += sizeof(uint32_t) * (size_t)d.ntiles;
+  HWO_CHECK(hipMemcpyAsync(d.tile_model, p, sizeof(uint32_t) * (size_t)d.ntiles, hipMemcpyHostToDevice, o->st));
+  p += sizeof(uint32_t) * (size_t)d.ntiles;
+  HWO_CHECK(hipMemcpyAsync(d.tile_ratio, p, sizeof(float) * (size_t)d.ntiles, hipMemcpyHostToDevice, o->st));
+  p += sizeof(float) * (size_t)d.ntiles;
+  if (hd.n_live > 0) HWO_CHECK(hipMemcpyAsync(S, p, rb * (size_t)hd.n_live, hipMemcpyHostToDevice, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  o->n_host = hd.n_host;
+  return HWO_OK;
+}
+
 int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int32_t on_device) {
   if (!o || n < 0 || n > (1 << 24) || (n > 0 && (!xy || !out))) return HWO_EINVAL;
   int rc = finalize(o);

@@ -21,7 +21,8 @@ STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "spla
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
-           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes"]
+           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes",
+           "hwo_snapshot_size", "hwo_snapshot", "hwo_restore"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -98,6 +99,9 @@ def lib():
         "hwo_time_stage": (C.c_int, [vp, i32, i32, P(C.c_double)]),
         "hwo_record_bytes": (i32, [vp]),
         "hwo_sample_probes": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float), i32]),
+        "hwo_snapshot_size": (C.c_int, [vp, P(i64)]),
+        "hwo_snapshot": (C.c_int, [vp, vp, i64]),
+        "hwo_restore": (C.c_int, [vp, vp, i64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -231,6 +235,19 @@ class Ocean:
     def normals(self, p: int) -> np.ndarray:
         """Unit normals (3, ny, nx) of patch p's blended map (needs normals=True)."""
         return np.stack([self.patch_map(p, layer) for layer in (2, 3, 4)])
+
+    def snapshot(self) -> bytes:
+        """Host image of the state at the current step boundary."""
+        n = C.c_int64()
+        self._check(self.L.hwo_snapshot_size(self.h, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        self._check(self.L.hwo_snapshot(self.h, buf, n.value))
+        return bytes(buf)
+
+    def restore(self, image: bytes):
+        """Continue from a snapshot of the same scene."""
+        buf = C.create_string_buffer(image, len(image))
+        self._check(self.L.hwo_restore(self.h, buf, len(image)))
 
     def sample_probes(self, xy) -> np.ndarray:
         """Height and unit normal (n, 4) of the current frame at world points xy (n, 2)."""

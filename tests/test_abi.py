@@ -98,6 +98,11 @@ def test_call_order_errors(L):
     assert L.hwo_sample_probes(h, xy, -1, out, 0) == hwo.HWO_EINVAL
     assert L.hwo_sample_probes(h, None, 2, out, 0) == hwo.HWO_EINVAL
     assert L.hwo_sample_probes(h, xy, 2, out, 0) == hwo.HWO_ESTATE   # no spectrum, no step
+    nbytes = C.c_int64()
+    assert L.hwo_snapshot_size(h, C.byref(nbytes)) == hwo.HWO_ESTATE   # nothing to save yet
+    img = (C.c_char * 16)()
+    assert L.hwo_snapshot(h, img, 16) == hwo.HWO_ESTATE
+    assert L.hwo_restore(h, img, 16) == hwo.HWO_EINVAL                # shorter than a header
     L.hwo_destroy_ocean(h)
     c2 = cfg(compact=1)
     assert L.hwo_create_ocean(C.byref(c2), C.byref(h)) == hwo.HWO_OK

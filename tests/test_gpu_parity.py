@@ -466,6 +466,42 @@ def test_probe_sampling(name, steps, form, synth):
         assert e <= TOL
 
 
+@pytest.mark.parametrize("name,form,synth", [("c2", "batched", 0), ("c3", "plain", 0), ("p0", "batched", 1)])
+def test_snapshot_and_resume(name, form, synth):
+    """Checkpoint / resume: k steps, snapshot, n - k more steps must equal a
+    fresh handle restored from the snapshot and stepped n - k times, and the
+    original handle restored and stepped again: integer state bit for bit,
+    heights up to FP32 summation order.  A snapshot of another scene is
+    refused."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.get(name).replace(synth=synth)
+    kw = dict(compact=True, batched=True) if form == "batched" else dict(compact=False, batched=False)
+    say(f"snapshot {name} {form} synth={synth}")
+    a = hwo.Ocean(s, **kw)
+    a.step(40)
+    img = a.snapshot()
+    a.step(25)
+    a.sync()
+    want_c = [a.counts(p) for p in range(len(s.patches))]
+    want_p = canon(a.particles())
+    want_h = [a.patch_map(p, 0) for p in range(len(s.patches))]
+    want_bg = a.background()
+    for g in (hwo.Ocean(s, **kw), a):
+        g.restore(img)
+        assert g.n == 40
+        g.step(25)
+        g.sync()
+        for p in range(len(s.patches)):
+            assert np.array_equal(g.counts(p), want_c[p])
+            assert rel_rms(g.patch_map(p, 0), want_h[p]) <= 1e-6
+        assert np.array_equal(canon(g.particles()), want_p)
+        assert np.array_equal(g.background(), want_bg)
+    other = hwo.Ocean(scenes.c1(), **kw)
+    other.step(1)
+    with pytest.raises(hwo.HwoError):
+        other.restore(img)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_capacity_overflow_reported():
     """More live particles than capacity: records beyond it are dropped,
