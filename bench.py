@@ -143,6 +143,36 @@ def measured_traffic(config, dom):
     return int(e["bytes_per_launch"]) if h == e["sources_sha256"] else None
 
 
+def copy_bandwidth(mib=512, reps=10):
+    """Achieved device-to-device copy bandwidth (read + write bytes / time),
+    the practical ceiling the HBM fractions can also be read against."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2.0 * mib * (1 << 20) / (ms * 1e-3) / 1e9
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(scene, preroll, nframes):
     """Time the FP64 oracle (one thread) on nframes full frames after the pre-roll."""
     import oracle
@@ -334,6 +364,12 @@ def main():
                     "avg_launch_ms": round(per_launch[dom], 5),
                     "algorithmic_bytes_per_launch": int(alg[dom])}
 
+    # achieved algorithmic bandwidth of the bandwidth-bound kernels, and the
+    # copy bandwidth of this device as a second reference
+    kernel_gbps = {k: round(alg[k] / (per_launch[k] * 1e-3) / 1e9, 1)
+                   for k in ("fft_a", "fft_b", "count", "scatter") if per_launch.get(k, 0.0) > 0}
+    copy_gbs = copy_bandwidth()
+
     if args.copy_mb > 0:
         # reference kernel of known traffic for hardware byte counters:
         # reads and writes exactly copy_mb MiB
@@ -352,7 +388,8 @@ def main():
         cms, csec = cpu_baseline(scene, preroll + W, nf)
         cpu = {"value": round(cms, 3), "unit": "ms/frame", "cores": 1, "kind": "oracle",
                "sample": f"{nf} full frames (bookkeeping, FP64 FFT background, splat and blend of every "
-                         f"patch) after frame {preroll + W}; {csec:.1f} s; host has {os.cpu_count()} cores"}
+                         f"patch) after frame {preroll + W}; {csec:.1f} s; one thread of {os.cpu_count()} "
+                         f"({cpu_model()})"}
         log(f"[bench] oracle {cms:.1f} ms/frame over {nf} frames")
 
     out = {
@@ -379,6 +416,8 @@ def main():
         "plain_fp32_ms_per_frame": round(plain_ms, 5) if plain_ms else None,
         "speedup_vs_plain": round(plain_ms / ms, 3) if plain_ms else None,
         "kernel_ms_per_frame": {k: round(v, 5) for k, v in per_frame.items()},
+        "kernel_gbps": kernel_gbps,
+        "copy_gbps": round(copy_gbs, 1),
         "kernel_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
