@@ -250,7 +250,7 @@ def p0() -> Scene:
     with amplitudes from S(w, theta); the group count per side pair is the
     paper's (no obliquity weighting).  The region follows a small moving
     source (a boat).
-    About 0.9M particles are live after the ~3600 steps that the slowest
+    About 0.54M particles are live after the ~3600 steps that the slowest
     waves need to cross the region.  Bin edges (cells) are chosen for this
     spectrum's bucket wavelengths (about 1.8-19.7 m, i.e. 9-101 cells)."""
     sp = Spectrum(U10=5.0, fetch=10e3, gamma=0.0, spread_s=-1.0, wind_dir=0.0,
