@@ -87,15 +87,17 @@ def algorithmic(scene, rec_bytes, n_live):
 def splat_flops(ocean, scene):
     """FP32 flops of the splat as a contraction: every crest and trough adds
     A w(d_x) w(d_y) to the cells of its (2 r / dx)^2 square footprint (on
-    average), one multiply-add per cell.  Radii come from the library's
+    average), one multiply-add per cell; the radial kernel reaches only the
+    disc of radius r, pi/4 of that square.  Radii come from the library's
     bucket table."""
     r = ocean.buckets()[:, 2]
+    area = math.pi / 4.0 if getattr(scene, "kernel", 0) == 1 else 1.0
     flops = 0.0
     for p, P in enumerate(scene.patches):
         live = ocean.counts(p, allow_overflow=True)[:, 0]
         for i in range(len(r)):
             rc = r[i] / P.dx
-            flops += float(live[i]) * 2.0 * (2.0 * rc) ** 2 * 2.0
+            flops += float(live[i]) * 2.0 * (2.0 * rc) ** 2 * 2.0 * area
     return flops
 
 
@@ -122,12 +124,12 @@ def layer_work(ocean, scene, rec_bytes, n_live):
     return {"deposit_x": (fx, bx), "filter_y": (fy, by), "layer_sum": (0.0, bs)}
 
 
-DOM_KERNEL = {"splat": "k_splat<RecCompact>", "fft_a": "k_fft_a", "fft_b": "k_fft_b",
+DOM_KERNEL = {"splat": "k_splat<RecCompact, false>", "fft_a": "k_fft_a", "fft_b": "k_fft_b",
               "count": "k_update<RecCompact, false>", "scatter": "k_update<RecCompact, true>",
               "deposit_x": "k_deposit_x<RecCompact>", "filter_y": "k_filter_y", "layer_sum": "k_layer_sum"}
 
 
-def measured_traffic(config, dom):
+def measured_traffic(config, dom, radial=False):
     """HBM bytes per launch of the dominant kernel from profiles/traffic.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
     reads for a device copy of known size), or None when there is no entry
@@ -137,7 +139,10 @@ def measured_traffic(config, dom):
     if not os.path.exists(path):
         return None
     e = json.load(open(path)).get(config)
-    if not e or e.get("kernel") != DOM_KERNEL.get(dom):
+    name = DOM_KERNEL.get(dom)
+    if radial and dom == "splat":
+        name = "k_splat<RecCompact, true>"
+    if not e or e.get("kernel") != name:
         return None
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in e["sources"])).hexdigest()
     return int(e["bytes_per_launch"]) if h == e["sources_sha256"] else None
@@ -250,6 +255,8 @@ def main():
                     help="paper-default scene over wind speeds and sampling densities (Table 2 trends)")
     ap.add_argument("--synth", type=int, default=0,
                     help="height synthesis: 0 exact-position splat, 1 the paper's texel layers")
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="crest/trough kernel: 0 separable w(dx) w(dy), 1 radial W(|d|) (exact splat only)")
     ap.add_argument("--copy-mb", type=int, default=0,
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -272,8 +279,9 @@ def main():
                           "unit": "ms/frame", "higher_is_better": False, "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "data": "synthetic", "trends": rows}), flush=True)
         return
-    scene = scenes.get(args.config).replace(synth=args.synth)
+    scene = scenes.get(args.config).replace(synth=args.synth, kernel=args.kernel)
     layers = args.synth == 1
+    radial = args.kernel == 1
     preroll = PREROLL.get(args.config, 0)
     K, W = args.steps, args.warmup
 
@@ -340,10 +348,11 @@ def main():
         flops_dom = flops if dom == "splat" else 0.0
     t_hbm = alg[dom] / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops_dom / (FP32_PEAK_TFLOPS * 1e12)
-    traffic = measured_traffic(args.config + ("-layers" if layers else ""), dom)
-    if layers and t_mfma > t_hbm:
-        # the layer passes are FP32 vector multiply-adds (no matrix cores):
-        # bound by the vector ALUs, FP32 vector peak 157.3 TFLOP/s
+    traffic = measured_traffic(args.config + ("-layers" if layers else "") + ("-radial" if radial else ""), dom,
+                               radial)
+    if (layers or radial) and t_mfma > t_hbm:
+        # the layer passes and the radial kernel are FP32 vector work (no
+        # matrix cores): bound by the vector ALUs, FP32 vector peak 157.3 TFLOP/s
         achieved = flops_dom / t / 1e12 if t > 0 else 0.0
         roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 5), "traffic": traffic,
@@ -410,6 +419,7 @@ def main():
                                f"frames {preroll + W + 1}..{preroll + W + K}",
                    "form": "16-byte records, batched launches, hipGraph",
                    "synthesis": "texel layers + separable passes" if layers else "exact-position splat",
+                   "kernel": "radial" if radial else "separable",
                    "live_particles": live, "preroll_frames": preroll},
         "splats_per_s": round(splats_per_s, 1) if splats_per_s else None,
         "fft_gbps": round(fft_gbs, 2) if fft_gbs else None,

@@ -82,6 +82,11 @@ typedef struct {
     int32_t bg_fields;      /* 1: the FFT also makes the background slopes dH/dx,
                                dH/dy and the choppy displacement (x, y), read as
                                layers 1-4 of the background; 0: height only */
+    int32_t kernel;         /* shape of the crest and trough kernel (Fig 1):
+                               0 separable w(dx) w(dy), w(d) = (1 + cos(pi d / r)) / 2
+                               for |d| < r; 1 radial W(|d|) with the same profile.
+                               The radial kernel needs synth 0 (the texel passes
+                               are separable); synth 1 with kernel 1 is HWO_EINVAL. */
 } hwo_config;
 
 /* Spectrum and bucket parameters (Sec 3.1, Sec 3.3). */

@@ -57,7 +57,7 @@ def lib():
         "orc_add_patch": (C.c_int, [vp, dbl, dbl, i32, i32, dbl, dbl, dbl, i32]),
         "orc_add_source": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32]),
         "orc_set_bins": (C.c_int, [vp, P(i32)]),
-        "orc_set_synthesis": (C.c_int, [vp, i32]),
+        "orc_set_synthesis": (C.c_int, [vp, i32, i32]),
         "orc_normals": (C.c_int, [vp, i32, P(dbl), P(dbl)]),
         "orc_background_field": (C.c_int, [vp, i32, dbl, P(dbl)]),
         "orc_sample_probes": (C.c_int, [vp, P(dbl), P(dbl), P(dbl), i64, P(dbl)]),
@@ -168,7 +168,7 @@ class Oracle:
         for s in scene.sources:
             self._check(self.L.orc_add_source(h, s.x0, s.y0, s.vx, s.vy, s.radius, s.draft,
                                               s.ring_n, s.patch))
-        self._check(self.L.orc_set_synthesis(h, int(getattr(scene, "synth", 0))))
+        self._check(self.L.orc_set_synthesis(h, int(getattr(scene, "synth", 0)), int(getattr(scene, "kernel", 0))))
         b = bins if bins is not None else scene.bins
         if b is not None:
             arr = np.ascontiguousarray(b, dtype=np.int32)

@@ -21,7 +21,8 @@
  *     over N_theta sectors (Sec 3.3),
  *     fixed-point analytic propagation at c_i, ring emission from moving
  *     sources into the closest-radius bucket (Sec 4.3), 3-way subdivision,
- *     and a separable raised-cosine crest/trough pair splat (Fig 1, Sec 4.2).
+ *     and a raised-cosine crest/trough pair splat (Fig 1, Sec 4.2), separable
+ *     w(dx) w(dy) or radial w(|d|).
  *   - Blend of patch and background with a smooth distance weight (Sec 3.1,
  *     Sec 4.2).
  * Where the paper is silent the readings are the ones listed in the design
@@ -86,6 +87,7 @@ struct orc_ocean {
     uint64_t seed;
     int have_spec, stepped, bins_set;
     int32_t synth;               /* 0 exact-position splat, 1 texel layers + separable passes */
+    int32_t kernel;              /* 0 separable w(dx) w(dy), 1 radial w(|d|) (synth 0 only) */
     double U10, fetch, gamma, s_const, wind_dir, alpha, wp, eta, subdiv_frac;
     int32_t nb, lmax, h0_mode, wind_code, dir_mode, flux_mode;
     double lam_min, lam_max;
@@ -1054,6 +1056,29 @@ static void splat_kernel(const orc_ocean *o, const patch_t *pt, double *raw, dou
     }
 }
 
+/* Radial variant of the same profile: add A * w(|x_c - c|) over the patch
+ * cells, with the distance taken in the plane rather than per axis. */
+static void splat_kernel_radial(const patch_t *pt, double *raw, double cxu, double cyu, double A, double r) {
+    double dxu = (double)pt->dxu;
+    double ru = r * UNIT;
+    int64_t i0 = (int64_t)floor((cxu - ru) / dxu) - pt->wx - 1;
+    int64_t i1 = (int64_t)ceil((cxu + ru) / dxu) - pt->wx + 1;
+    int64_t j0 = (int64_t)floor((cyu - ru) / dxu) - pt->wy - 1;
+    int64_t j1 = (int64_t)ceil((cyu + ru) / dxu) - pt->wy + 1;
+    if (i0 < 0) i0 = 0;
+    if (j0 < 0) j0 = 0;
+    if (i1 > pt->nx - 1) i1 = pt->nx - 1;
+    if (j1 > pt->ny - 1) j1 = pt->ny - 1;
+    for (int64_t j = j0; j <= j1; ++j) {
+        double yc = (double)((pt->wy + j) * pt->dxu + pt->dxu / 2);
+        for (int64_t i = i0; i <= i1; ++i) {
+            double xc = (double)((pt->wx + i) * pt->dxu + pt->dxu / 2);
+            double rho = hypot(xc - cxu, yc - cyu) / UNIT;
+            raw[(size_t)j * pt->nx + i] += A * wker(rho, r);
+        }
+    }
+}
+
 /* Crest +A at the particle, trough -A one radius behind it along its
  * direction (the positive-negative pair of Fig 1). */
 static void splat_particle(const orc_ocean *o, const patch_t *pt, double *raw, const prt_t *q,
@@ -1064,6 +1089,11 @@ static void splat_particle(const orc_ocean *o, const patch_t *pt, double *raw, c
     double A = amplitude(o, q);
     double ang = 2.0 * M_PI * (double)q->code / (double)NCODE;
     double tx = r * cos(ang) * UNIT, ty = r * sin(ang) * UNIT;
+    if (o->kernel == 1) {
+        splat_kernel_radial(pt, raw, (double)px, (double)py, A, r);
+        splat_kernel_radial(pt, raw, (double)px - tx, (double)py - ty, -A, r);
+        return;
+    }
     splat_kernel(o, pt, raw, (double)px, (double)py, A, r, wxv, wyv);
     splat_kernel(o, pt, raw, (double)px - tx, (double)py - ty, -A, r, wxv, wyv);
 }
@@ -1141,9 +1171,12 @@ static void layer_synth(const orc_ocean *o, const patch_t *pt, double *raw, cons
     }
 }
 
-int orc_set_synthesis(orc_ocean *o, int32_t mode) {
+int orc_set_synthesis(orc_ocean *o, int32_t mode, int32_t kernel) {
     if (mode != 0 && mode != 1) return fail(o, "synthesis mode must be 0 or 1");
+    if (kernel != 0 && kernel != 1) return fail(o, "kernel must be 0 or 1");
+    if (kernel == 1 && mode != 0) return fail(o, "the radial kernel needs the exact-position synthesis");
     o->synth = mode;
+    o->kernel = kernel;
     return 0;
 }
 

@@ -37,9 +37,11 @@ int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, do
 int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,
                    double draft, int32_t ring_n, int32_t patch);
 int orc_set_bins(orc_ocean *o, const int32_t *bin_cells);
-/* Height synthesis: 0 the exact-position separable splat, 1 texel layers per
- * bucket (bilinear deposit) smoothed by separable x and y passes (Sec 4.2). */
-int orc_set_synthesis(orc_ocean *o, int32_t mode);
+/* Height synthesis: 0 the exact-position splat, 1 texel layers per bucket
+ * (bilinear deposit) smoothed by separable x and y passes (Sec 4.2).
+ * kernel: 0 the separable product w(dx) w(dy), 1 the radial w(|d|) with the
+ * same raised-cosine profile (Fig 1); the radial kernel needs mode 0. */
+int orc_set_synthesis(orc_ocean *o, int32_t mode, int32_t kernel);
 /* Unit normals of patch p from height map h (ny x nx) by finite differences
  * (Sec 4.2); out holds three ny x nx planes: x, y and z components. */
 int orc_normals(orc_ocean *o, int32_t p, const double *h, double *out);

@@ -167,6 +167,7 @@ struct Dev {
   float *partials;             // [max_items][kTile * kTile] partial tiles of split tiles
   int32_t max_items;           // capacity of partials (items)
   uint32_t chunk_load;         // least estimated cost of a work item
+  int32_t radial;              // 1: radial kernel W(|d|) instead of w(dx) w(dy) (exact splat only)
   // texel-layer synthesis (synth == 1)
   int32_t synth;
   int32_t n_xtiles;            // 64 x 64 tiles of all x-filtered layers

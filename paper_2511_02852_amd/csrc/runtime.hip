@@ -212,6 +212,8 @@ int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out) {
   if (cfg->synth != 0 && cfg->synth != 1) return HWO_EINVAL;
   if (cfg->normals != 0 && cfg->normals != 1) return HWO_EINVAL;
   if (cfg->bg_fields != 0 && cfg->bg_fields != 1) return HWO_EINVAL;
+  if (cfg->kernel != 0 && cfg->kernel != 1) return HWO_EINVAL;
+  if (cfg->kernel == 1 && cfg->synth != 0) return HWO_EINVAL;
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return HWO_EINVAL;
   hwo_ocean *o = new hwo_ocean();
   o->cfg = *cfg;
@@ -734,6 +736,7 @@ static int finalize(hwo_ocean *o) {
   if (!d.item_desc) return o->fail(HWO_ENOMEM, "device allocation failed");
   d.partials = (float *)o->alloc(sizeof(float) * (size_t)kTile * kTile * (size_t)d.max_items);
   d.synth = o->cfg.synth;
+  d.radial = o->cfg.kernel;
   if (d.synth == 1 && np > 0) {
     d.n_xtiles = o->xt_base.back();
     // trough offsets round(r (cos, sin) 2^20): the texel a trough lands in is an integer decision

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) 
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanLdsTiles = 8192;   // tiles whose item prefix fits in LDS for the parallel fill
 constexpr int kFusedMaxTiles = 4096;  // tiles of a scene that k_bin_plan handles
-constexpr int kFusedMaxBins = 65536;  // bins of a scene that k_bin_plan handles
+constexpr int kFusedMaxBins = 16384;  // bins of a scene that k_bin_plan handles (offsets held in LDS)
 
 // Body of the plan, run by one block of kPlanThreads threads; load[t] is the
 // model cost estimate of tile t0 + t (global memory or LDS).  It is first
@@ -257,38 +257,51 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
 // cursors, cleared histogram, totals), then the cost estimate of every tile
 // from the new offsets, then the plan.  Replaces the two scan launches, the
 // load launch and the plan launch when all bins and tiles fit one block.
+// The histogram is staged in LDS with coalesced loads (several in flight per
+// thread) and scanned there, so the estimates read the offsets from LDS
+// rather than back from memory.
 __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int nt, int items_target) {
   __shared__ uint32_t s_load[kFusedMaxTiles];
+  __shared__ int32_t s_off[kFusedMaxBins + 1];
   __shared__ int32_t s_w[kPlanThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // ---- scan: each thread a run of consecutive bins
+#pragma unroll 8
+  for (int i = tid; i < nbins; i += kPlanThreads) s_off[i] = d.hist[i];
+  for (int t = tid; t < nt; t += kPlanThreads) s_load[t] = 0;
+  __syncthreads();
+  // ---- scan: each thread a run of consecutive bins, in place
   const int per = (nbins + kPlanThreads - 1) / kPlanThreads;
   const int beg = min(nbins, tid * per), end = min(nbins, beg + per);
   int32_t sum = 0;
-  for (int i = beg; i < end; ++i) sum += d.hist[i];
+  for (int i = beg; i < end; ++i) sum += s_off[i];
   int32_t inc = sum;
   for (int o = 1; o < 64; o <<= 1) {
     const int32_t y = __shfl_up(inc, o);
     if (lane >= o) inc += y;
   }
   if (lane == 63) s_w[wv] = inc;
-  for (int t = tid; t < nt; t += kPlanThreads) s_load[t] = 0;
   __syncthreads();
   int32_t acc = inc - sum;
   for (int w = 0; w < wv; ++w) acc += s_w[w];
   for (int i = beg; i < end; ++i) {
-    const int32_t v = d.hist[i];
-    d.off[i] = acc;
-    d.cur[i] = acc;
-    d.hist[i] = 0;
+    const int32_t v = s_off[i];
+    s_off[i] = acc;
     acc += v;
   }
   if (tid == kPlanThreads - 1) {
-    d.off[nbins] = acc;
+    s_off[nbins] = acc;
     d.glob->total = acc;
     d.glob->n_live = min(acc, d.cap);
   }
   __syncthreads();
+  for (int i = tid; i <= nbins; i += kPlanThreads) {
+    const int32_t v = s_off[i];
+    d.off[i] = v;
+    if (i < nbins) {
+      d.cur[i] = v;
+      d.hist[i] = 0;
+    }
+  }
   // ---- tile cost estimates: one (tile, bucket) pair per thread
   for (int q = tid; q < nt * d.nb; q += kPlanThreads) {
     const int t = q / d.nb, b = q % d.nb;
@@ -297,7 +310,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int
     uint32_t seen = 0;
     for (int r = 0; r < rc.w; ++r) {
       const int rb = P.binbase[b] + (rc.z + r) * P.nbx[b];
-      seen += (uint32_t)max(0, min(d.off[rb + rc.y + 1], d.cap) - min(d.off[rb + rc.x], d.cap));
+      seen += (uint32_t)max(0, min(s_off[rb + rc.y + 1], d.cap) - min(s_off[rb + rc.x], d.cap));
     }
     if (seen) atomicAdd(&s_load[t], seen * visit_cost(d.bucket_r[b] / (float)P.dx));
   }
@@ -346,7 +359,37 @@ __device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv
   }
 }
 
-template <class Rec>
+// Radial kernel W(|d|), small footprints: as splat_points, one point per lane,
+// the weight of each cell from its distance to the point.
+template <int F>
+__device__ __forceinline__ void splat_points_radial(float (*acc)[kPad], const float4 pv, bool valid, float rc,
+                                                    float qs, int tw, int th) {
+  int ilo = 0, jlo = 0, nc = 0, nr = 0;
+  if (valid && pv.z != 0.f) {
+    ilo = max(0, (int)ceilf(pv.x - rc));
+    jlo = max(0, (int)ceilf(pv.y - rc));
+    nc = min(F, min(tw - 1, (int)floorf(pv.x + rc)) - ilo + 1);
+    nr = min(F, min(th - 1, (int)floorf(pv.y + rc)) - jlo + 1);
+  }
+  const float dx0 = (float)ilo - pv.x, dy0 = (float)jlo - pv.y;
+#pragma unroll
+  for (int jj = 0; jj < F; ++jj) {
+    if (!__any(jj < nr)) break;
+    const float dy = dy0 + (float)jj;
+    float *row = &acc[min(jlo + jj, kTile - 1)][ilo];
+#pragma unroll
+    for (int ii = 0; ii < F; ++ii) {
+      if (!__any(ii < nc)) break;
+      const float dx = dx0 + (float)ii;
+      const float w = wrev(__builtin_amdgcn_sqrtf(dx * dx + dy * dy) * qs);
+      if (jj < nr && ii < nc && w != 0.f) atomicAdd(row + ii, pv.z * w);
+    }
+  }
+}
+
+// kRadial selects the radial kernel W(|d|); it is a template parameter so
+// that the separable kernel's register allocation does not carry it.
+template <class Rec, bool kRadial>
 // At most 102 registers per lane: five wavefronts per SIMD (five blocks per CU).
 __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
                                                     int ndirect, float *__restrict__ raw_out,
@@ -497,7 +540,38 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
         const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
         const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
         const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
-        if (span <= 7) {
+        if constexpr (kRadial) {
+          // ---- radial kernel: not a sum of outer products, so no matrix cores
+          if (span <= 7) {
+            for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
+              const int q = q0 + lane;
+              const bool valid = q < q_hi;
+              const float4 pv = pt[valid ? q : q_lo];
+              if (span <= 3) splat_points_radial<4>(acc, pv, valid, rc, qs, T.tw, T.th);
+              else splat_points_radial<8>(acc, pv, valid, rc, qs, T.tw, T.th);
+            }
+          } else if (quad_live) {
+            // large footprints: the wavefront's quadrant accumulates in
+            // registers, each lane the 16 cells it holds in the matrix-core
+            // layout (column xq + lane % 32, rows yq + 8 (r / 4) + 4 (lane / 32) + r % 4)
+            const float dxl = (float)(xq + (lane & 31)), ybase = (float)(yq + 4 * (lane >> 5));
+            for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
+              const int q = q0 + lane;
+              const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
+              uint64_t mask = __ballot(hit);
+              while (mask) {   // wave-uniform
+                const float4 pv = pt[q0 + __builtin_ctzll(mask)];
+                mask &= mask - 1;
+                const float dx = dxl - pv.x, dx2 = dx * dx;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                  const float dy = ybase + (float)(8 * (r >> 2) + (r & 3)) - pv.y;
+                  cq[r] += pv.z * wrev(__builtin_amdgcn_sqrtf(dx2 + dy * dy) * qs);
+                }
+              }
+            }
+          }
+        } else if (span <= 7) {
           // ---- small footprints: points spread over all wavefronts
           for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
             const int q = q0 + lane;
@@ -650,14 +724,27 @@ void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipS
   hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, st, d, nbins, ntiles, items_target);
 }
 
+// The splat kernel for the record form and kernel shape of d.
+template <bool kRadial>
+void splat_launch(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,
+                  int64_t out_off, hipStream_t st) {
+  if (d.compact)
+    hipLaunchKernelGGL((k_splat<RecCompact, kRadial>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+                       (const RecCompact *)recs, n, raw, blend, out_off);
+  else
+    hipLaunchKernelGGL((k_splat<RecWide, kRadial>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+                       (const RecWide *)recs, n, raw, blend, out_off);
+}
+
+void splat_launch_any(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,
+                      int64_t out_off, hipStream_t st) {
+  if (d.radial) splat_launch<true>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+  else splat_launch<false>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+}
+
 void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st) {
   if (ntiles <= 0) return;
-  if (d.compact)
-    hipLaunchKernelGGL(k_splat<RecCompact>, dim3(grid), dim3(kThreads), 0, st, d, t0, ntiles,
-                       (const RecCompact *)nullptr, 0, d.raw, d.blend, (int64_t)0);
-  else
-    hipLaunchKernelGGL(k_splat<RecWide>, dim3(grid), dim3(kThreads), 0, st, d, t0, ntiles, (const RecWide *)nullptr,
-                       0, d.raw, d.blend, (int64_t)0);
+  splat_launch_any(d, dim3(grid), t0, ntiles, nullptr, 0, d.raw, d.blend, (int64_t)0, st);
 }
 
 void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st) {
@@ -668,12 +755,7 @@ void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st) {
 void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw, int64_t out_off,
                          hipStream_t st) {
   if (ntiles <= 0) return;
-  if (d.compact)
-    hipLaunchKernelGGL(k_splat<RecCompact>, dim3(ntiles), dim3(kThreads), 0, st, d, t0, ntiles,
-                       (const RecCompact *)recs, n, raw, (float *)nullptr, out_off);
-  else
-    hipLaunchKernelGGL(k_splat<RecWide>, dim3(ntiles), dim3(kThreads), 0, st, d, t0, ntiles, (const RecWide *)recs, n,
-                       raw, (float *)nullptr, out_off);
+  splat_launch_any(d, dim3(ntiles), t0, ntiles, recs, n, raw, (float *)nullptr, out_off, st);
 }
 
 }  // namespace hwo

@@ -33,7 +33,7 @@ class HwoConfig(C.Structure):
                 ("seed", C.c_uint64), ("compact", C.c_int32), ("batched", C.c_int32), ("stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("max_particles", C.c_int64), ("synth", C.c_int32), ("normals", C.c_int32),
-                ("bg_fields", C.c_int32)]
+                ("bg_fields", C.c_int32), ("kernel", C.c_int32)]
 
 
 class HwoSpectrum(C.Structure):
@@ -168,6 +168,7 @@ class Ocean:
             cfg.dev_free = self._alloc.free_cb
         cfg.max_particles = int(max_particles)
         cfg.synth = int(getattr(scene, "synth", 0))
+        cfg.kernel = int(getattr(scene, "kernel", 0))
         cfg.normals = int(bool(normals))
         cfg.bg_fields = int(bool(bg_fields))
         self._cfg = cfg

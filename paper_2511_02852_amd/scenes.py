@@ -120,6 +120,8 @@ class Scene:
     batched: bool = False
     # height synthesis: 0 exact-position splat, 1 texel layers + separable passes
     synth: int = 0
+    # crest/trough kernel shape: 0 separable w(dx) w(dy), 1 radial W(|d|) (synth 0 only)
+    kernel: int = 0
 
     def replace(self, **kw) -> "Scene":
         return dataclasses.replace(self, **kw)

@@ -61,7 +61,8 @@ def test_create_validates_config(L):
     h = C.c_void_p()
     assert L.hwo_create_ocean(None, C.byref(h)) == hwo.HWO_EINVAL
     for bad in (dict(fft_n=100), dict(fft_n=8), dict(fft_n=8192), dict(fft_L=0.0), dict(g=-1.0),
-                dict(dt=0.0), dict(max_particles=-5), dict(synth=2), dict(normals=3), dict(bg_fields=2)):
+                dict(dt=0.0), dict(max_particles=-5), dict(synth=2), dict(normals=3), dict(bg_fields=2),
+                dict(kernel=2), dict(kernel=1, synth=1)):
         assert L.hwo_create_ocean(C.byref(cfg(**bad)), C.byref(h)) == hwo.HWO_EINVAL, bad
     assert L.hwo_create_ocean(C.byref(cfg()), C.byref(h)) == hwo.HWO_OK
     assert h.value

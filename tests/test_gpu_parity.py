@@ -392,6 +392,56 @@ def test_gpu_texel_layers_random_particles(compact):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("compact", [False, True])
+def test_gpu_radial_kernel_random_particles(compact):
+    """The radial kernel W(|d|) through the test hook: hand-placed boundary
+    and ring particles of every bucket (small footprints one point per lane,
+    large ones one point per wavefront), c2 geometry, against the oracle."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.c2().replace(kernel=1)
+    g = hwo.Ocean(s, compact=compact)
+    o = oracle.Oracle(s)
+    g.step(1)
+    o.step(1)
+    wx, wy = o.window(0)
+    rng = np.random.default_rng(6)
+    dxu = int(0.25 * 2 ** 20)
+    si = o.source_info(0)
+    recs = []
+    for k in range(3000):
+        kind = int(rng.random() < 0.3)
+        b = si["bucket"] if kind else int(rng.integers(0, 8))
+        level = int(rng.integers(0, 3)) if kind else 0
+        x = int((wx + rng.uniform(-10, 266)) * dxu)
+        y = int((wy + rng.uniform(-10, 266)) * dxu)
+        code = int(rng.integers(0, 10368))
+        birth = int(rng.integers(0, 2))
+        recs.append([0, b, kind, level, code, birth, x, y, 0 if kind else -1, int(rng.integers(0, 64)) if kind else 0])
+    recs = np.array(recs)
+    say(f"radial kernel random particles compact={compact}")
+    h = g.test_splat(0, recs)
+    ref = o.splat(0, recs)
+    e = rel_rms(h, ref)
+    say(f"radial random rel rms {e:.2e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "batched"),
+                                             ("p0", 40, "batched"), ("c3", 12, "batched")])
+def test_radial_kernel_scenes(name, steps, form):
+    """Scenes with the radial kernel: integer state bit-exact (the kernel
+    shape touches heights only) and heights against the oracle."""
+    s = scenes.get(name).replace(kernel=1)
+    kw = dict(compact=True, batched=True) if form == "batched" else {}
+    say(f"radial kernel {name} {form} {steps} steps")
+    g, o = make(s, **kw)
+    g.step(steps)
+    o.step(steps)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s)
+    say(f"radial kernel {name} {form} err={e}")
+
+
 @pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "plain"),
                                              ("c2", 60, "batched"), ("p0", 40, "batched"),
                                              ("c3", 12, "batched"), ("c3", 12, "plain")])

@@ -107,6 +107,63 @@ def test_single_particle_closed_form():
     assert np.max(np.abs(h - want)) <= 1e-14
 
 
+def radial_scene():
+    """One bucket with lambda = 4 m, r = 2 m = 8 cells of 0.25 m, radial kernel."""
+    return pin_scene(lam=(2.0, 8.0)).replace(kernel=1)
+
+
+def test_radial_kernel_depends_on_distance_only():
+    """Fig 1 profile taken as a radial W(|d|): in front of a crest moving
+    along +x the trough (one radius behind) contributes nothing, so every
+    cell at the same distance from the crest holds the same value -- here the
+    lattice points at distance 5 cells: (3, 4), (4, 3), (5, 0), (0, 5) and
+    their mirror images in y.  The separable product gives w(3)w(4) != w(5)w(0)."""
+    s = radial_scene()
+    o = oracle.Oracle(s)
+    assert o.bucket(0)["r"] == pytest.approx(2.0)
+    A = o.patch_bucket(0, 0)["A"]
+    dxu = int(0.25 * UNIT)
+    i0, j0 = 30, 31
+    h = o.splat(0, np.array([rec(i0 * dxu + dxu // 2, j0 * dxu + dxu // 2, 0)]))
+    vals = [h[j0 + dy, i0 + dx] for dx, dy in ((3, 4), (4, 3), (5, 0), (0, 5), (3, -4), (4, -3), (0, -5))]
+    assert min(vals) > 0.05 * A
+    assert max(vals) - min(vals) <= 1e-14 * A
+    sep = oracle.Oracle(pin_scene(lam=(2.0, 8.0)))
+    hs = sep.splat(0, np.array([rec(i0 * dxu + dxu // 2, j0 * dxu + dxu // 2, 0)]))
+    assert abs(hs[j0 + 4, i0 + 3] - hs[j0, i0 + 5]) > 0.02 * A   # 0.346 A vs 0.309 A
+
+
+def test_radial_kernel_volume_and_moment():
+    """The pair has zero volume (crest and trough sample the kernel at the
+    same sub-cell offsets when r is a whole number of cells along an axis) and
+    first moment A V r along its direction, where V is the crest's volume in
+    cells; V tends to the integral of the raised cosine over the disc,
+    r^2 (pi/2 - 2/pi), within 5e-4 at r = 8 cells (midpoint rule)."""
+    s = radial_scene()
+    o = oracle.Oracle(s)
+    r = o.bucket(0)["r"]
+    A = o.patch_bucket(0, 0)["A"]
+    p = s.patches[0]
+    rc = r / p.dx
+    xc = (np.arange(p.nx) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, xc)
+    disc = rc * rc * (math.pi / 2 - 2 / math.pi)
+    for code, ux, uy in ((0, 1, 0), (oracle.NCODE // 4, 0, 1), (oracle.NCODE // 2, -1, 0)):
+        px, py = 8.13, 7.71
+        h = o.splat(0, np.array([rec(int(px * UNIT), int(py * UNIT), code)]))
+        assert abs(h.sum()) <= 1e-12 * A * disc
+        V = ((h * X).sum() * ux + (h * Y).sum() * uy) / (A * r)
+        assert V == pytest.approx(disc, rel=5e-4)
+        assert abs(V - rc * rc) > 0.05 * rc * rc   # not the separable kernel's (r/dx)^2
+
+
+def test_radial_kernel_validation():
+    s = radial_scene()
+    for bad in (s.replace(kernel=2), s.replace(synth=1)):
+        with pytest.raises(oracle.OracleError):
+            oracle.Oracle(bad)
+
+
 # ---------------------------------------------------------------- blend
 def test_blend_limits_and_bilinear():
     """Sec 3.1 local replacement: a vanishing blend band gives the pure WP map
