@@ -4,9 +4,9 @@ Each case draws (from its seed, inputs only) a spectrum with log-spaced or
 equal-energy buckets, inverse-CDF or stratified directions, the literal or
 obliquity-weighted injection count, Gaussian or unit-modulus h0, constant
 or Mitsuyasu spreading; one to three patches with sizes that are not
-multiples of the 64-cell tile, static or following a source; the exact or
-the texel-layer synthesis; wide or compact records; per-patch or batched
-launches.  Integer state must be bit-exact and heights within 1e-4 RMS.
+multiples of the 64-cell tile, static or following a source; the exact
+(separable or radial kernel) or the texel-layer synthesis; wide or compact
+records; per-patch or batched launches.  Integer state must be bit-exact and heights within 1e-4 RMS.
 """
 import math
 
@@ -51,9 +51,11 @@ def random_scene(seed):
     N = int(rng.choice([64, 128, 256]))
     compact = bool(rng.integers(0, 2))
     batched = bool(rng.integers(0, 2))
+    synth = int(rng.integers(0, 2))
+    kernel = int(rng.integers(0, 2)) if synth == 0 else 0
     return scenes.Scene(name=f"sweep{seed}", fft_n=N, fft_L=N * 2.0, seed=seed, steps=0, spectrum=sp,
                         patches=patches, sources=sources, bins=[32] * nb, compact=compact, batched=batched,
-                        synth=int(rng.integers(0, 2)))
+                        synth=synth, kernel=kernel)
 
 
 @pytest.mark.parametrize("seed", range(16))
@@ -62,7 +64,7 @@ def test_random_scene(seed):
     s = random_scene(seed)
     sp = s.spectrum
     say(f"sweep {seed}: buckets={sp.n_buckets} bucket_mode={sp.bucket_mode} dir_mode={sp.dir_mode} "
-        f"flux_mode={sp.flux_mode} synth={s.synth} compact={s.compact} batched={s.batched} "
+        f"flux_mode={sp.flux_mode} synth={s.synth} kernel={s.kernel} compact={s.compact} batched={s.batched} "
         f"patches={[(p.nx, p.ny, p.dx) for p in s.patches]} sources={len(s.sources)} N={s.fft_n}")
     # bin edges from the bucket radii: a 64-cell tile must reach its crests
     # through at most 32 bin rows (the library's documented limit)
