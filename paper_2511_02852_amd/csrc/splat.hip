@@ -18,10 +18,14 @@
 // total item budget) and a prefix of work items (k_bin_plan does the scan,
 // the estimates and the plan in one block for small scenes).  k_splat is a
 // grid over the
-// items: an item is one part of one tile, i.e. one of `nparts` equal shares
-// of each bucket's list of particles that can reach the tile.  That list is
-// the bins whose crests lie within 2 r_b of the tile, contiguous runs of the
-// bin-sorted particle buffer.  The item decodes 256 particles at a time into
+// items: an item is one part of one tile.  Each bucket's list of particles
+// that can reach the tile is cut into blocks of kSplit consecutive entries
+// (one 128-byte line of 16-byte records) and part j of `nparts` takes blocks
+// j, j + nparts, ...: every part samples the whole tile, so its four
+// quadrants get about equal work (contiguous shares gave each part a band of
+// bin rows), while a record line is still read by one part only.  That list
+// is the bins whose crests lie within 2 r_b of the tile, contiguous runs of
+// the bin-sorted particle buffer.  The item decodes 256 particles at a time into
 // LDS (crest and trough centres in tile cells, signed amplitudes) and then
 // runs each bucket's run of points through one of two paths:
 //   * footprints of at most 7 cells per axis: one point per lane, weights in
@@ -321,6 +325,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int
 // ---------------------------------------------------------------- splat
 constexpr int kChunk = kThreads;   // particles decoded into LDS per step
 constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
+constexpr int kSplit = 8;          // entries per block when a tile's lists are dealt to its parts
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
   __shared__ int s_rlo[kMaxBuckets][kMaxRows];
   __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
   __shared__ int s_nrows[kMaxBuckets];
-  __shared__ int s_bstart[kMaxBuckets];      // first index of this part in the bucket's list
+  __shared__ int s_bstart[kMaxBuckets];      // first block of this part in the bucket's list
   __shared__ int s_boff[kMaxBuckets + 1];    // offsets of the buckets in the item's list
   __shared__ int s_tile, s_part, s_nparts, s_patch;
 
@@ -470,10 +475,13 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
       int accum = 0;
       for (int b = 0; b < nb; ++b) {
         const int M = s_pre[b][s_nrows[b]];
-        const int p0 = (int)((int64_t)M * part / nparts), p1 = (int)((int64_t)M * (part + 1) / nparts);
-        s_bstart[b] = p0;
+        // blocks part, part + nparts, ... of kSplit entries; the last block may be short
+        const int nblk = (M + kSplit - 1) / kSplit;
+        int cnt = nblk > part ? (nblk - part + nparts - 1) / nparts * kSplit : 0;
+        if (nblk > 0 && (nblk - 1) % nparts == part) cnt -= nblk * kSplit - M;
+        s_bstart[b] = part;
         s_boff[b] = accum;
-        accum += p1 - p0;
+        accum += cnt;
       }
       s_boff[nb] = accum;
     }
@@ -495,7 +503,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
         const int g = c + tid;
         int b = 0;
         while (b + 1 < nb && s_boff[b + 1] <= g) ++b;
-        const int v = s_bstart[b] + (g - s_boff[b]);
+        const int gl = g - s_boff[b];
+        const int v = (s_bstart[b] + gl / kSplit * nparts) * kSplit + gl % kSplit;
         int lo = 0, hi = s_nrows[b] - 1;   // last row with prefix <= v
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
