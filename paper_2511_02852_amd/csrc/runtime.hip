@@ -98,7 +98,7 @@ struct hwo_ocean {
   uint32_t *cdf = nullptr, *cdfQ = nullptr;
   int update_grid = 1024;
   int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
-  int items_target = 4096;          // splat work items per frame the plan aims for (beyond one per tile)
+  int items_target = 4096;          // splat work items per frame the plan aims for (beyond one per tile; set per scene)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // batched form: the background FFT runs on a second branch of the frame
@@ -693,7 +693,13 @@ static int finalize(hwo_ocean *o) {
   }
   // splat work plan
   d.max_items = d.ntiles + 8192;
-  d.chunk_load = 2500;   // least estimated cost per work item (a few hundred particle visits)
+  d.chunk_load = 3500;   // least estimated cost per work item (several hundred particle visits)
+  // Items beyond one per tile: about 16 parts per tile on average, between
+  // 1024 and 4096.  Every extra part writes a 16 KiB partial tile that the
+  // reduce reads back, so scenes with few dense tiles do better with fewer,
+  // larger parts, while scenes with thousands of tiles of uneven load need
+  // the larger budget to cut their heavy tiles.
+  o->items_target = std::min(4096, std::max(1024, 16 * d.ntiles));
   d.tile_load = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
   d.tile_meas = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
   d.tile_model = (uint32_t *)o->alloc(sizeof(uint32_t) * (size_t)std::max(d.ntiles, 1));
