@@ -340,7 +340,7 @@ void launch_scan(const Dev &d, int bin_lo, int bin_hi, bool first, bool last, hi
 void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipStream_t st);
 void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st);
 // Fused scan + tile estimates + plan for a whole small scene (one block).
-bool bin_plan_fits(int nbins, int ntiles);
+bool bin_plan_fits(int nbins, int ntiles, int nb);
 void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipStream_t st);
 void launch_splat_reduce(const Dev &d, int t0, int ntiles, hipStream_t st);
 void launch_splat_direct(const Dev &d, int t0, int ntiles, const void *recs, int n, float *raw,

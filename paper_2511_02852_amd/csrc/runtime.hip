@@ -804,7 +804,7 @@ static int finalize(hwo_ocean *o) {
   o->update_grid = std::max(64, 6 * cus);   // six blocks per CU are resident (75 registers per lane)
   o->target_blocks = std::max(64, 4 * cus);
   if (o->cfg.batched) {
-    o->fused = bin_plan_fits(d.nbins, d.ntiles);
+    o->fused = bin_plan_fits(d.nbins, d.ntiles, d.nb);
     HWO_CHECK(hipStreamCreateWithFlags(&o->st2, hipStreamNonBlocking));
     HWO_CHECK(hipEventCreateWithFlags(&o->ev_fork, hipEventDisableTiming));
     HWO_CHECK(hipEventCreateWithFlags(&o->ev_join, hipEventDisableTiming));

@@ -113,15 +113,18 @@ __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) 
 // One block: parts per tile from the loads, prefix of work items.
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanLdsTiles = 8192;   // tiles whose item prefix fits in LDS for the parallel fill
-constexpr int kFusedMaxTiles = 4096;  // tiles of a scene that k_bin_plan handles
+constexpr int kFusedMaxTiles = 1024;  // tiles of a scene that k_bin_plan handles (one per thread)
 constexpr int kFusedMaxBins = 16384;  // bins of a scene that k_bin_plan handles (offsets held in LDS)
 
 // Body of the plan, run by one block of kPlanThreads threads; load[t] is the
 // model cost estimate of tile t0 + t (global memory or LDS).  It is first
 // corrected by the splat time measured for the tile in the previous frame:
 // each tile keeps a running average of (measured / estimated) relative to the
-// whole scene, and load[t] is scaled by it in place.
-__device__ void plan_items(const Dev &d, int t0, int nt, int items_target, uint32_t *load) {
+// whole scene, and load[t] is scaled by it in place.  meas, model and ratio
+// are that state for tiles t0.. as read at the start (global memory or an LDS
+// copy); the updated state is written to global memory.
+__device__ void plan_items(const Dev &d, int t0, int nt, int items_target, uint32_t *load, const uint32_t *meas,
+                           const uint32_t *model, const float *ratio) {
   __shared__ uint64_t s_red[kPlanThreads / 64];
   __shared__ uint64_t s_red2[kPlanThreads / 64];
   __shared__ float s_gm;
@@ -137,7 +140,7 @@ __device__ void plan_items(const Dev &d, int t0, int nt, int items_target, uint3
   {
     uint64_t ms = 0, es = 0;
     for (int t = beg; t < end; ++t) {
-      const uint32_t m = d.tile_meas[t0 + t], e = d.tile_model[t0 + t];
+      const uint32_t m = meas[t], e = model[t];
       if (m && e) {
         ms += m;
         es += e;
@@ -163,8 +166,8 @@ __device__ void plan_items(const Dev &d, int t0, int nt, int items_target, uint3
     __syncthreads();
     const float gm = s_gm;
     for (int t = beg; t < end; ++t) {
-      const uint32_t m = d.tile_meas[t0 + t], e = d.tile_model[t0 + t];
-      float r = d.tile_ratio[t0 + t];
+      const uint32_t m = meas[t], e = model[t];
+      float r = ratio[t];
       if (gm > 0.f && m && e) r = fminf(4.f, fmaxf(0.25f, 0.5f * r + 0.5f * ((float)m / (float)e) / gm));
       d.tile_ratio[t0 + t] = r;
       d.tile_meas[t0 + t] = 0;
@@ -254,7 +257,7 @@ __device__ void plan_items(const Dev &d, int t0, int nt, int items_target, uint3
 }
 
 __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int nt, int items_target) {
-  plan_items(d, t0, nt, items_target, d.tile_load + t0);
+  plan_items(d, t0, nt, items_target, d.tile_load + t0, d.tile_meas + t0, d.tile_model + t0, d.tile_ratio + t0);
 }
 
 // Small scenes, one block: exclusive scan of the bin histogram (offsets,
@@ -266,15 +269,40 @@ __global__ __launch_bounds__(kPlanThreads) void k_splat_plan(Dev d, int t0, int 
 // rather than back from memory.
 __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int nt, int items_target) {
   __shared__ uint32_t s_load[kFusedMaxTiles];
+  __shared__ uint32_t s_meas[kFusedMaxTiles], s_model[kFusedMaxTiles];
+  __shared__ float s_ratio[kFusedMaxTiles];
   __shared__ int32_t s_off[kFusedMaxBins + 1];
   __shared__ int32_t s_w[kPlanThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // Every load the block needs is issued here, in one round: the histogram,
+  // the previous frame's state of the tiles (one tile per thread) and the
+  // geometry of the (tile, bucket) pair whose estimate this thread makes.
+  const int nb = d.nb;
+  const bool est = tid < nt * nb;   // nt * nb <= kPlanThreads (bin_plan_fits)
+  int e_t = 0, e_base = 0, e_nbx = 0;
+  short4 e_rc = make_short4(0, 0, 0, 0);
+  uint32_t e_cost = 0;
+  if (est) {
+    const int b = tid % nb;
+    e_t = tid / nb;
+    const PatchDev &P = d.patches[d.tile_patch[e_t]];
+    e_rc = d.tile_rect[(size_t)e_t * nb + b];
+    e_base = P.binbase[b];
+    e_nbx = P.nbx[b];
+    e_cost = visit_cost(d.bucket_r[b] / (float)P.dx);
+  }
+  if (tid < nt) {
+    s_meas[tid] = d.tile_meas[tid];
+    s_model[tid] = d.tile_model[tid];
+    s_ratio[tid] = d.tile_ratio[tid];
+    s_load[tid] = 0;
+  }
 #pragma unroll 8
   for (int i = tid; i < nbins; i += kPlanThreads) s_off[i] = d.hist[i];
-  for (int t = tid; t < nt; t += kPlanThreads) s_load[t] = 0;
   __syncthreads();
-  // ---- scan: each thread a run of consecutive bins, in place
-  const int per = (nbins + kPlanThreads - 1) / kPlanThreads;
+  // ---- scan: each thread a run of consecutive bins, in place; an odd run
+  //      length keeps the threads of a wavefront on distinct LDS banks
+  const int per = ((nbins + kPlanThreads - 1) / kPlanThreads) | 1;
   const int beg = min(nbins, tid * per), end = min(nbins, beg + per);
   int32_t sum = 0;
   for (int i = beg; i < end; ++i) sum += s_off[i];
@@ -306,20 +334,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int
       d.hist[i] = 0;
     }
   }
-  // ---- tile cost estimates: one (tile, bucket) pair per thread
-  for (int q = tid; q < nt * d.nb; q += kPlanThreads) {
-    const int t = q / d.nb, b = q % d.nb;
-    const PatchDev &P = d.patches[d.tile_patch[t]];
-    const short4 rc = d.tile_rect[(size_t)t * d.nb + b];
+  // ---- tile cost estimates: one (tile, bucket) pair per thread, from LDS
+  if (est) {
     uint32_t seen = 0;
-    for (int r = 0; r < rc.w; ++r) {
-      const int rb = P.binbase[b] + (rc.z + r) * P.nbx[b];
-      seen += (uint32_t)max(0, min(s_off[rb + rc.y + 1], d.cap) - min(s_off[rb + rc.x], d.cap));
+    for (int r = 0; r < e_rc.w; ++r) {
+      const int rb = e_base + (e_rc.z + r) * e_nbx;
+      seen += (uint32_t)max(0, min(s_off[rb + e_rc.y + 1], d.cap) - min(s_off[rb + e_rc.x], d.cap));
     }
-    if (seen) atomicAdd(&s_load[t], seen * visit_cost(d.bucket_r[b] / (float)P.dx));
+    if (seen) atomicAdd(&s_load[e_t], seen * e_cost);
   }
   __syncthreads();
-  plan_items(d, 0, nt, items_target, s_load);
+  plan_items(d, 0, nt, items_target, s_load, s_meas, s_model, s_ratio);
 }
 
 // ---------------------------------------------------------------- splat
@@ -727,7 +752,9 @@ void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipSt
   hipLaunchKernelGGL(k_splat_plan, dim3(1), dim3(kPlanThreads), 0, st, d, t0, ntiles, items_target);
 }
 
-bool bin_plan_fits(int nbins, int ntiles) { return nbins <= kFusedMaxBins && ntiles <= kFusedMaxTiles; }
+bool bin_plan_fits(int nbins, int ntiles, int nb) {
+  return nbins <= kFusedMaxBins && ntiles <= kFusedMaxTiles && (int64_t)ntiles * nb <= kPlanThreads;
+}
 
 void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipStream_t st) {
   hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, st, d, nbins, ntiles, items_target);
