@@ -34,7 +34,10 @@
  * pair-lattice cosine sum, crest volume, subdivision conservation, blend
  * limits, equal-energy bucket integrals, stratified sector balance and the
  * direction amplitude factor's normalisation, the steady-state spectral
- * density of obliquity-weighted injection.  Full-scene particle bookkeeping beyond these is parity unpinned
+ * density of obliquity-weighted injection, the bin histogram against a
+ * histogram of the crest positions, window recentring within half a cell of
+ * the source track and ring origins on the source position.  Full-scene
+ * particle bookkeeping beyond these is parity unpinned
  * except through the identities tested there.
  */
 #include "oracle.h"

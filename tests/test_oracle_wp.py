@@ -712,3 +712,101 @@ def test_probe_sampling_exact_for_planes_and_grid_points():
     sx = -np.sin(k * jx * dxf) * math.sin(k * dxf) / dxf
     assert np.max(np.abs(out[:, 1] - (-sx / np.sqrt(1 + sx * sx)))) <= 1e-12
     assert np.max(np.abs(out[:, 2])) <= 1e-12
+
+
+# ---------------------------------------------------------------- bins and windows
+def crest_positions(o, P, n):
+    """Crest positions origin + floor(age V / 4096), V from the (separately
+    pinned) velocity table, vectorised over the particle set."""
+    key = P[:, 1] * oracle.NCODE + P[:, 4]
+    uk, inv = np.unique(key, return_inverse=True)
+    V = np.array([o.velocity(int(k // oracle.NCODE), int(k % oracle.NCODE)) for k in uk],
+                 dtype=np.int64).reshape(-1, 2)
+    age = n - P[:, 5]
+    px = P[:, 6] + np.floor_divide(age * V[inv, 0], 4096)
+    py = P[:, 7] + np.floor_divide(age * V[inv, 1], 4096)
+    return px, py
+
+
+@pytest.mark.parametrize("name,steps", [("c2", 400), ("c1", 16)])
+def test_bin_histogram_is_histogram2d_of_crests(name, steps):
+    """The per-(patch, bucket) bin histogram (the counting-sort key of the
+    binning step) equals numpy.histogram2d of the crest positions -- not the
+    troughs -- over bins of the stated edge, anchored at the window origin
+    minus the bucket margin 2 r, with nbx = floor((nx dx + 2 m) / edge) + 1
+    bins per row.  c2 has a window that follows its source (400 steps, splits
+    included); c1's patch is static."""
+    s = scenes.get(name)
+    o = oracle.Oracle(s)
+    o.step(steps)
+    n = o.n
+    P = o.particles()
+    pt = s.patches[0]
+    dxu = int(round(pt.dx * UNIT))
+    wx, wy = o.window(0)
+    px, py = crest_positions(o, P, n)
+    checked = 0
+    for b in range(o.nb):
+        sel = P[:, 1] == b
+        m = int(math.ceil(2.0 * o.bucket(b)["r"] * UNIT))
+        assert m == o.bucket(b)["margin_u"]
+        edge = s.bins[b] * dxu
+        lox, loy = wx * dxu - m, wy * dxu - m
+        nbx = (pt.nx * dxu + 2 * m) // edge + 1
+        nby = (pt.ny * dxu + 2 * m) // edge + 1
+        assert o.tile_dims(0, b) == (s.bins[b], nbx, nby)
+        ex = lox + edge * np.arange(nbx + 1, dtype=np.float64)
+        ey = loy + edge * np.arange(nby + 1, dtype=np.float64)
+        want, _, _ = np.histogram2d(py[sel].astype(np.float64), px[sel].astype(np.float64), bins=[ey, ex])
+        assert want.sum() == sel.sum(), "a crest fell outside the expanded window"
+        assert np.array_equal(o.tiles(0, b), want.astype(np.int64)), f"bucket {b}"
+        checked += int(sel.sum())
+    assert checked == P.shape[0] and checked > 1000
+
+
+@pytest.mark.parametrize("name,steps", [("c2", 600), ("p0", 600)])
+def test_window_follows_source_within_half_cell(name, steps):
+    """A patch that follows its source recentres in whole cells every step:
+    the window centre anchor + (W + n/2) dx stays within half a cell of the
+    source position x0 + v n dt, and moves by at most one cell per step at
+    these speeds (below one cell per step).  Stepped one step at a time with
+    one particle per group (the windows do not depend on the particles)."""
+    s = scenes.get(name)
+    s = s.replace(spectrum=dataclasses.replace(s.spectrum, eta=1.0))
+    o = oracle.Oracle(s)
+    pt, src = s.patches[0], s.sources[0]
+    assert pt.follow == 0
+    prev = None
+    for n in range(1, steps + 1):
+        o.step(1)
+        wx, wy = o.window(0)
+        cx = pt.anchor_x + (wx + pt.nx / 2) * pt.dx
+        cy = pt.anchor_y + (wy + pt.ny / 2) * pt.dx
+        xs = src.x0 + src.vx * n * s.dt
+        ys = src.y0 + src.vy * n * s.dt
+        assert abs(cx - xs) <= 0.5 * pt.dx + 1e-9, (n, cx, xs)
+        assert abs(cy - ys) <= 0.5 * pt.dx + 1e-9, (n, cy, ys)
+        if prev is not None:
+            assert abs(wx - prev[0]) <= 1 and abs(wy - prev[1]) <= 1
+        prev = (wx, wy)
+    # the window really moved
+    assert abs(prev[0]) + abs(prev[1]) > 10
+
+
+def test_ring_origin_is_source_position():
+    """Ring particles start on a circle of radius R around the source's
+    position at their birth step, x0 + v n dt (anchor-relative, 2^-20 m):
+    origin - R (cos, sin)(2 pi j / n_e) is within one unit of it."""
+    s = scenes.c2()
+    o = oracle.Oracle(s)
+    o.step(100)
+    P = o.particles()
+    ring = P[P[:, 2] == 1]
+    pt, src = s.patches[0], s.sources[0]
+    assert ring.shape[0] > 64
+    for q in ring[::7]:
+        n, j = int(q[5]), int(q[9])
+        phi = 2 * math.pi * j / src.ring_n
+        ex = (src.x0 + src.vx * n * s.dt - pt.anchor_x) * UNIT + src.radius * math.cos(phi) * UNIT
+        ey = (src.y0 + src.vy * n * s.dt - pt.anchor_y) * UNIT + src.radius * math.sin(phi) * UNIT
+        assert abs(q[6] - ex) <= 1.0 and abs(q[7] - ey) <= 1.0, (q, ex, ey)
