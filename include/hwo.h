@@ -133,45 +133,79 @@ typedef struct {
     int32_t patch;          /* patch receiving the particles */
 } hwo_source;
 
-/* Create a handle.  Validates the config; allocates nothing on the device. */
+/* Create a handle for one ocean.  The configuration carries the inputs the
+ * paper's pipeline takes besides the spectrum (Sec 4.1, Fig 3): the FFT
+ * background grid and period, gravity, the time step and the seed of the
+ * random draws, plus the record form, the launch form and the synthesis and
+ * kernel options.  Validates cfg; allocates nothing on the device.  *out
+ * receives the handle (owned by the caller until hwo_destroy_ocean).
+ * HWO_EINVAL for a NULL argument or an invalid field (grid not a power of two
+ * in 16..4096, non-positive period, g or dt, unknown mode). */
 int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out);
+/* Release every device allocation and the handle (Sec 4.1 pipeline state);
+ * NULL is ignored.  The caller must not use o afterwards. */
 void hwo_destroy_ocean(hwo_ocean *o);
+/* Message of the last failing call on o (the status codes above, Sec 4.1
+ * pipeline); owned by the handle, valid until the next call on it. */
 const char *hwo_last_error(const hwo_ocean *o);
 
-/* Spectrum, buckets, direction tables, h0(k) and twiddles (FP64 on the GPU,
- * stored FP32).  Once per handle, before add_patch / add_source. */
+/* Spectrum and buckets (Sec 3.1 Eq 1-6; Sec 3.2 kinematics r_i = pi g / w_i^2,
+ * c_i = g / w_i; Sec 3.3 buckets, Eq 7 amplitude, Eq 18 rates): builds the
+ * bucket, direction and velocity tables, h0(k) and the FFT twiddles (FP64 on
+ * the GPU, stored FP32).  Once per handle, before add_patch / add_source
+ * (HWO_ESTATE otherwise); HWO_EINVAL for out-of-range parameters. */
 int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp);
-/* Add a patch (max 127); *id receives its index.  HWO_EINVAL for a bad size or
- * dx, and, with dir_mode 1, for an effective eta that is not a whole number in
- * 1..10368 (one direction code per particle at most). */
+/* Add a wave-particle patch, the rectangular region around an interactive
+ * object where the particle field replaces the FFT (Sec 3.1 local
+ * replacement; boundary injection Sec 3.3, Eq 18).  Max 127 patches; *id
+ * receives its index (dense, in call order; it selects the patch's RNG
+ * streams).  HWO_EINVAL for a bad size or dx, and, with dir_mode 1, for an
+ * effective eta that is not a whole number in 1..10368 (one direction code
+ * per particle at most); HWO_ESTATE after the first step. */
 int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id);
-/* Add a moving source (max 127) emitting into patch src->patch. */
+/* Add a moving object that disturbs the water (Sec 4.3, object acts on
+ * water): a disc emitting rings of particles into patch src->patch, into the
+ * bucket whose radius is closest to the disc's.  Max 127; *id receives its
+ * index.  HWO_EINVAL for a bad patch index, radius or ring size;
+ * HWO_ESTATE after the first step. */
 int hwo_add_source(hwo_ocean *o, const hwo_source *s, int32_t *id);
-/* Per-bucket particle bin edge in cells (n == n_buckets, each 1..4096).
- * Optional; changes only the bin histogram, never heights or other counts. */
+/* Per-bucket particle bin edge in cells (n == n_buckets, each 1..4096) of
+ * the counting sort that groups particles for the per-bucket splat (Sec 4.2
+ * per-bucket layers).  Optional; changes only the bin histogram, never
+ * heights or other counts.  HWO_ESTATE after the first step. */
 int hwo_set_bins(hwo_ocean *o, const int32_t *bin_cells, int32_t n);
 
-/* Advance nsteps frames (asynchronous).  The first call allocates device
- * memory and fixes the scene. */
+/* Advance nsteps frames of the pipeline (Sec 4.1, Fig 3): FFT background,
+ * boundary injection, ring emission, propagation and subdivision, binning,
+ * per-bucket splat and blend.  Asynchronous on the library stream.  The
+ * first call allocates device memory and fixes the scene.  HWO_EINVAL for
+ * nsteps < 0, HWO_ERANGE if the step index would pass 2^31 - 1,
+ * HWO_EDEVICE for a HIP failure. */
 int hwo_step(hwo_ocean *o, int32_t nsteps);
+/* Wait for the frames issued by hwo_step (Sec 4.1 pipeline). */
 int hwo_sync(hwo_ocean *o);
+/* Frames issued so far: heights describe t = n dt (Sec 4.1); -1 for NULL. */
 int64_t hwo_step_index(const hwo_ocean *o);
 
 /* Copy a height map (FP32, row-major [y][x]) into dst (host or device memory
- * per dst_is_device).  which = -1: background N x N, layer 0 the height,
+ * per dst_is_device), the outputs of the blend (Sec 3.1 stitching, Sec 4.2
+ * composition of FFT and particle heights).  which = -1: background N x N
+ * (Sec 4.1), layer 0 the height,
  * 1 dH/dx, 2 dH/dy, 3 and 4 the choppy displacement sum -i (k/|k|) h~
  * e^{ik.x} in x and y (HWO_ESTATE unless hwo_config.bg_fields; these fields
  * omit the Nyquist rows and columns); which = p >= 0: patch p
  * (ny x nx) with layer 0 = blended, 1 = raw wave-particle height, 2, 3, 4 =
  * x, y, z component of the unit normal of the blended map (central
  * differences, one-sided at the patch edges; HWO_ESTATE unless
- * hwo_config.normals).  Syncs. */
+ * hwo_config.normals).  HWO_ERANGE if dst_elems is too small.  Syncs. */
 int hwo_read_heightmaps(hwo_ocean *o, int32_t which, int32_t layer, float *dst,
                         int64_t dst_elems, int32_t dst_is_device);
 
-/* Per bucket of patch p, six int64: live, injected, emitted, subdivided,
- * died, dropped (capacity overflow, whole ocean).  dst_elems >= 6 n_buckets.
- * Returns HWO_EOVERFLOW (with valid counts) if particles were dropped. */
+/* Particle bookkeeping of patch p (Sec 3.3 injection counts, Eq 18; Sec 4.3
+ * ring emission), six int64 per bucket: live, injected, emitted,
+ * subdivided, died, dropped (capacity overflow, whole ocean).
+ * dst_elems >= 6 n_buckets, else HWO_ERANGE.  Returns HWO_EOVERFLOW (with
+ * valid counts) if particles were dropped. */
 int hwo_read_counts(hwo_ocean *o, int32_t patch, int64_t *dst, int64_t dst_elems);
 
 /* Frequency buckets after set_spectrum (Sec 3.2-3.3): four doubles per bucket,
@@ -179,22 +213,28 @@ int hwo_read_counts(hwo_ocean *o, int32_t patch, int64_t *dst, int64_t dst_elems
  * speed c_i = g / w_i (m/s); bucket 0 holds the shortest waves.  n >= 4
  * n_buckets, else HWO_ERANGE; HWO_ESTATE before set_spectrum. */
 int hwo_read_buckets(const hwo_ocean *o, double *dst, int32_t n);
-/* Bin grid of (patch, bucket): dims = {bin edge cells, nbx, nby}. */
+/* Bin grid of (patch, bucket) used to group particles for the per-bucket
+ * splat (Sec 4.2): dims = {bin edge cells, nbx, nby}.  HWO_ERANGE for a bad
+ * index, HWO_ESTATE before the first step. */
 int hwo_tile_dims(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dims);
-/* Live particles per bin, row-major [by][bx], bins anchored at the window
- * origin minus the bucket margin 2 r. */
+/* Live particles per bin (Sec 4.2 per-bucket grouping), row-major [by][bx],
+ * bins anchored at the window origin minus the bucket margin 2 r.
+ * HWO_ERANGE if n < nbx nby. */
 int hwo_read_tiles(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dst, int64_t n);
 
-/* Live particles as canonical records of 10 int64:
+/* Live particles (Sec 3.2 single particle: direction, frequency bucket,
+ * amplitude source) as canonical records of 10 int64:
  * patch, bucket, kind (0 boundary, 1 ring), level, code (units of
  * 2 pi / 10368), birth step, origin x, origin y (2^-20 m from the patch
  * anchor), source (-1 boundary), ring slot.  *n_out receives the count;
  * fails with HWO_ERANGE if max_recs is too small. */
 int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_out);
 
-/* Test hook: splat caller-placed canonical records into patch p's raw map at
- * the current step (no binning), result in dst (host, ny x nx).  With synth 1
- * the records go through the texel layers instead (which it overwrites). */
+/* Test hook: splat caller-placed canonical records (the crest/trough pair of
+ * Fig 1, Sec 3.2) into patch p's raw map at the current step (no binning),
+ * result in dst (host, ny x nx).  With synth 1 the records go through the
+ * texel layers instead (which it overwrites).  HWO_EINVAL for a record of
+ * another patch or an out-of-range field; HWO_ESTATE before the first step. */
 int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, float *dst,
                    int64_t dst_elems);
 
@@ -208,33 +248,37 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * the first step; n at most 2^24.  Syncs. */
 int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int32_t on_device);
 
-/* Checkpoint and resume.  A snapshot is a host-memory image of the state at
- * the current step boundary (step index, counters, bin offsets, live particle
- * records, splat partition feedback) plus a fingerprint of the scene.
+/* Checkpoint and resume of the pipeline state (Sec 4.1, Fig 3: the state
+ * one frame hands to the next).  A snapshot is a host-memory image of the
+ * state at the current step boundary (step index, counters, bin offsets, live
+ * particle records, splat partition feedback) plus a fingerprint of the scene.
  * hwo_snapshot_size gives its size in bytes (HWO_ESTATE before the first
  * step); hwo_snapshot writes it into dst (HWO_ERANGE if dst_bytes is too
  * small); hwo_restore loads an image into a handle built with the same scene,
  * configuration and record form (HWO_EINVAL otherwise), after which stepping
  * continues exactly as from the saved step: integer state bit for bit,
- * heights up to FP32 summation order.  Heights read before the next step are
- * those the handle held before restoring.  The caller owns both buffers.
- * All three synchronise the stream. */
+ * heights up to FP32 summation order.  Heights, probes and test splats read
+ * between a restore and the next step describe the restored step index's
+ * windows; the height maps are those the handle held before restoring.  The
+ * caller owns both buffers.  All three synchronise the stream. */
 int hwo_snapshot_size(hwo_ocean *o, int64_t *bytes);
 int hwo_snapshot(hwo_ocean *o, void *dst, int64_t dst_bytes);
 int hwo_restore(hwo_ocean *o, const void *src, int64_t src_bytes);
 
-/* Per-stage timing (benchmark support).  enable != 0 brackets every kernel
- * launch with HIP events (graph replay is then disabled); hwo_stage_times
- * returns accumulated milliseconds and launch counts per stage:
+/* Per-stage timing, benchmark support for the frame-time measurements of
+ * Sec 5.2 (Table 2).  enable != 0 brackets every kernel launch with HIP
+ * events (graph replay is then disabled); hwo_stage_times returns
+ * accumulated milliseconds and launch counts per stage:
  *   0 params  1 fft_a  2 fft_b  3 count  4 scan  5 scatter  6 splat
  *   7 splat_plan  8 splat_reduce  9 bin_plan  10 deposit_x  11 filter_y
  *   12 layer_sum  13 normals (n >= 14).  bin_plan is the one-block scan + tile
  *   estimates + plan that replaces stages 4 and 7 in the batched form of
- *   scenes with at most 65536 bins and 4096 tiles.  Stages 6-8 run with
- *   synth 0, stages 10-12 with synth 1. */
+ *   scenes with at most 16384 bins, 1024 output tiles and 1024 (tile, bucket)
+ *   pairs.  Stages 6-8 run with synth 0, stages 10-12 with synth 1. */
 int hwo_set_timing(hwo_ocean *o, int32_t enable);
 int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
-/* Benchmark support: after at least one step, launch the kernels of one
+/* Benchmark support (Sec 5.2 frame-time measurements): after at least one
+ * step, launch the kernels of one
  * stage reps times back to back between two HIP events on the library stream
  * and store the mean milliseconds per repetition (all launch groups of the
  * stage).  Only stages whose kernels are idempotent for a finished frame are
@@ -244,7 +288,9 @@ int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
  * HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are rewritten
  * with the same values (up to FP32 summation order). */
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep);
-/* Bytes of particle storage per record for the active form (16 or 32). */
+/* Bytes of particle storage per record for the active form (16 or 32): the
+ * particle attributes of Sec 3.2 (position, direction, bucket, amplitude
+ * source, birth); -1 for NULL. */
 int32_t hwo_record_bytes(const hwo_ocean *o);
 
 #ifdef __cplusplus

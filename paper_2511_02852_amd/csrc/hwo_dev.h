@@ -335,6 +335,8 @@ void launch_h0(const Dev &d, float2 *h0T, float2 *tw, double alpha, double wp, d
 void launch_fft_a(const Dev &d, hipStream_t st);
 void launch_fft_b(const Dev &d, hipStream_t st);
 void launch_params(const Dev &d, hipStream_t st);
+// Windows of every patch at the current step (no advance).
+void launch_windows(const Dev &d, hipStream_t st);
 void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st);
 void launch_scan(const Dev &d, int bin_lo, int bin_hi, bool first, bool last, hipStream_t st);
 void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipStream_t st);

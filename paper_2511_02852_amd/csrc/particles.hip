@@ -63,6 +63,54 @@ __device__ int32_t block_scan_excl(int32_t *a, int len, int32_t *s_w /* kThreads
   return total;
 }
 
+// ---------------------------------------------------------------- windows
+// Window of patch p at step n (a patch that follows a source recentres in
+// whole cells on the source's FP64 position), its background offsets and the
+// range of its previous particles in the input buffer.  The injection and
+// emission ranges are left to the caller.
+__device__ void patch_window(const Dev &d, int p, int64_t n, StepPatch &W) {
+  const double tn = (double)n * d.dt;
+  const PatchDev &P = d.patches[p];
+  int64_t wx = 0, wy = 0;
+  if (P.follow >= 0) {
+    const SourceDev &S = d.sources[P.follow];
+    const double xs = S.x0 + S.vx * tn;
+    const double ys = S.y0 + S.vy * tn;
+    wx = round_away((xs - P.ax) / P.dx) - P.nx / 2;
+    wy = round_away((ys - P.ay) / P.dx) - P.ny / 2;
+  }
+  W.wx = (int32_t)wx;
+  W.wy = (int32_t)wy;
+  // keep every window (with a 64 m margin) inside the int32 position range
+  const int64_t lim = (int64_t)1 << 31;
+  const int64_t reach = (int64_t)64 << 20;
+  if (wx * P.dxu - reach < -lim || (wx + P.nx) * P.dxu + reach >= lim ||
+      wy * P.dxu - reach < -lim || (wy + P.ny) * P.dxu + reach >= lim)
+    atomicOr(&d.glob->err, 1);
+  const double X = P.ax + (double)(wx * P.dxu + P.dxu / 2) * (1.0 / 1048576.0);
+  const double Y = P.ay + (double)(wy * P.dxu + P.dxu / 2) * (1.0 / 1048576.0);
+  const double u = X / d.dxf, v = Y / d.dxf;
+  const double fu = floor(u), fv = floor(v);
+  const int64_t N = d.N;
+  W.gx0 = (int32_t)((((int64_t)fu % N) + N) % N);
+  W.gy0 = (int32_t)((((int64_t)fv % N) + N) % N);
+  W.fx0 = (float)(u - fu);
+  W.fy0 = (float)(v - fv);
+  W.ex_lo = min(d.off[P.bin_lo], d.cap);
+  W.ex_hi = min(d.off[P.bin_hi], d.cap);
+}
+
+// Windows of every patch at the current step without advancing it (after a
+// restore, so that reads before the next step see the restored step).
+__global__ __launch_bounds__(kThreads) void k_windows(Dev d) {
+  const int64_t n = d.glob->n;
+  for (int p = threadIdx.x; p < d.np; p += kThreads) {
+    StepPatch W = d.sp[p];
+    patch_window(d, p, n, W);
+    d.sp[p] = W;
+  }
+}
+
 // ---------------------------------------------------------------- k_params
 __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
   __shared__ int64_t s_n;
@@ -79,35 +127,8 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
 
   // windows, background offsets, previous-particle ranges
   for (int p = tid; p < d.np; p += kThreads) {
-    const PatchDev &P = d.patches[p];
-    int64_t wx = 0, wy = 0;
-    if (P.follow >= 0) {
-      const SourceDev &S = d.sources[P.follow];
-      const double xs = S.x0 + S.vx * tn;
-      const double ys = S.y0 + S.vy * tn;
-      wx = round_away((xs - P.ax) / P.dx) - P.nx / 2;
-      wy = round_away((ys - P.ay) / P.dx) - P.ny / 2;
-    }
     StepPatch W;
-    W.wx = (int32_t)wx;
-    W.wy = (int32_t)wy;
-    // keep every window (with a 64 m margin) inside the int32 position range
-    const int64_t lim = (int64_t)1 << 31;
-    const int64_t reach = (int64_t)64 << 20;
-    if (wx * P.dxu - reach < -lim || (wx + P.nx) * P.dxu + reach >= lim ||
-        wy * P.dxu - reach < -lim || (wy + P.ny) * P.dxu + reach >= lim)
-      atomicOr(&d.glob->err, 1);
-    const double X = P.ax + (double)(wx * P.dxu + P.dxu / 2) * (1.0 / 1048576.0);
-    const double Y = P.ay + (double)(wy * P.dxu + P.dxu / 2) * (1.0 / 1048576.0);
-    const double u = X / d.dxf, v = Y / d.dxf;
-    const double fu = floor(u), fv = floor(v);
-    const int64_t N = d.N;
-    W.gx0 = (int32_t)((((int64_t)fu % N) + N) % N);
-    W.gy0 = (int32_t)((((int64_t)fv % N) + N) % N);
-    W.fx0 = (float)(u - fu);
-    W.fy0 = (float)(v - fv);
-    W.ex_lo = min(d.off[P.bin_lo], d.cap);
-    W.ex_hi = min(d.off[P.bin_hi], d.cap);
+    patch_window(d, p, n, W);
     d.sp[p] = W;
   }
 
@@ -505,6 +526,10 @@ void launch_cdf(const Dev &d, const uint32_t *q, uint32_t *cdf, uint32_t *cdfQ, 
 // ---------------------------------------------------------------- launchers
 void launch_params(const Dev &d, hipStream_t st) {
   hipLaunchKernelGGL(k_params, dim3(1), dim3(kThreads), 0, st, d);
+}
+
+void launch_windows(const Dev &d, hipStream_t st) {
+  hipLaunchKernelGGL(k_windows, dim3(1), dim3(kThreads), 0, st, d);
 }
 
 void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st) {

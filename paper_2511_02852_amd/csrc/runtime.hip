@@ -784,6 +784,7 @@ static int finalize(hwo_ocean *o) {
       !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
     return o->fail(HWO_ENOMEM, "device allocation failed");
   HWO_CHECK(hipMemsetAsync(d.glob, 0, sizeof(Globals), o->st));
+  HWO_CHECK(hipMemsetAsync(d.sp, 0, sizeof(StepPatch) * std::max(np, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.ctr, 0, sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.hist, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.off, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
@@ -1341,6 +1342,11 @@ int hwo_restore(hwo_ocean *o, const void *src, int64_t src_bytes) {
   HWO_CHECK(hipMemcpyAsync(d.tile_ratio, p, sizeof(float) * (size_t)d.ntiles, hipMemcpyHostToDevice, o->st));
   p += sizeof(float) * (size_t)d.ntiles;
   if (hd.n_live > 0) HWO_CHECK(hipMemcpyAsync(S, p, rb * (size_t)hd.n_live, hipMemcpyHostToDevice, o->st));
+  // windows of the restored step, for probes and test splats before the next step
+  if (d.np > 0) {
+    launch_windows(d, o->st);
+    HWO_CHECK(hipGetLastError());
+  }
   HWO_CHECK(hipStreamSynchronize(o->st));
   o->n_host = hd.n_host;
   return HWO_OK;

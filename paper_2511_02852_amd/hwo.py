@@ -116,18 +116,25 @@ def _p(a, ct):
 
 
 class _TorchAllocator:
-    """Device memory from PyTorch's caching allocator, kept alive by pointer."""
+    """Device memory from PyTorch's caching allocator, kept alive by pointer.
 
-    def __init__(self):
+    Blocks are allocated with the library's stream current, so the caching
+    allocator associates them with that stream: a block is only handed out
+    again to allocations on the same stream, which are ordered after every
+    library kernel that used it."""
+
+    def __init__(self, stream):
         import torch
         self.torch = torch
+        self.stream = stream
         self.live = {}
         self.alloc_cb = ALLOC_FN(self._alloc)
         self.free_cb = FREE_FN(self._free)
 
     def _alloc(self, nbytes, ctx):
         try:
-            t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
+            with self.torch.cuda.stream(self.stream):
+                t = self.torch.empty(int(nbytes), dtype=self.torch.uint8, device="cuda")
         except Exception:
             return None
         ptr = t.data_ptr()
@@ -163,7 +170,7 @@ class Ocean:
             self._stream = stream
             cfg.stream = C.c_void_p(stream.cuda_stream)
         if torch_memory:
-            self._alloc = _TorchAllocator()
+            self._alloc = _TorchAllocator(self._stream)
             cfg.dev_alloc = self._alloc.alloc_cb
             cfg.dev_free = self._alloc.free_cb
         cfg.max_particles = int(max_particles)

@@ -34,6 +34,38 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def declaration_blocks():
+    """(comment, [function names]) for every run of declarations in the
+    header after the type definitions: each run of consecutive prototypes
+    and the comment block directly above it."""
+    text = open(os.path.join(ROOT, "include", "hwo.h")).read()
+    body = text[text.index("} hwo_source;"):]
+    blocks = []
+    comment, names = None, []
+    for tok in re.finditer(r"/\*.*?\*/|[^;/]*?\b(hwo_[a-z_]+)\s*\([^;]*;", body, flags=re.S):
+        if tok.group(0).startswith("/*"):
+            if names:
+                blocks.append((comment, names))
+                names = []
+            comment = tok.group(0)
+        elif tok.group(1):
+            names.append(tok.group(1))
+    if names:
+        blocks.append((comment, names))
+    return blocks
+
+
+def test_every_declaration_cites_the_paper():
+    """Every declaration block of the boundary names the passage that defines
+    its operation (a Sec, Eq, Fig or Table tag of the paper)."""
+    blocks = declaration_blocks()
+    covered = sorted({n for _, ns in blocks for n in ns})
+    assert covered == declared_functions()
+    for comment, names in blocks:
+        assert comment, f"{names}: no comment"
+        assert re.search(r"\b(Sec|Eq|Fig|Table) \d", comment), f"{names}: no citation in {comment[:80]!r}"
+
+
 def test_every_declared_symbol_is_exported(L):
     from paper_2511_02852_amd import hwo
     names = declared_functions()

@@ -552,6 +552,26 @@ def test_snapshot_and_resume(name, form, synth):
         other.restore(img)
 
 
+def test_restore_sets_the_windows_of_the_restored_step():
+    """A fresh handle restored from a snapshot of a moving-window scene (c2)
+    evaluates test splats in the windows of the restored step before any
+    further step: the same records splat to the same map as on the handle
+    the snapshot was taken from."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.c2()
+    a = hwo.Ocean(s, compact=True, batched=True)
+    a.step(40)
+    img = a.snapshot()
+    P = a.particles()
+    recs = P[np.random.default_rng(5).choice(P.shape[0], 2000, replace=False)]
+    want = a.test_splat(0, recs)
+    b = hwo.Ocean(s, compact=True, batched=True)
+    b.restore(img)
+    got = b.test_splat(0, recs)
+    assert np.abs(want).max() > 0
+    assert rel_rms(got, want) <= 1e-6
+
+
 @pytest.mark.parametrize("name,synth", [("c2", 0), ("c3", 0), ("p0", 1)])
 def test_repeated_runs_agree(name, synth):
     """Race check: LDS atomics, wavefront-aggregated counters and the
