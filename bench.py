@@ -1,22 +1,25 @@
 """Benchmark of the per-frame hybrid-ocean hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5]
 
 A step is one frame: FFT background (evolve + two LDS FFT passes), particle
 update (subdivide / survive / inject / emit, bin count, scan, scatter) and the
 per-bucket splat with the blend epilogue, for every patch of the scene.
 
-The default workload is the single-patch scene at realistic size (FFT 512^2
-over 1 km, one 256^2 patch at 0.25 m following a ship-like source, 8
-buckets).  The scene is first pre-rolled (untimed) to frame 540 of its
-600-frame run so the timed frames see the steady particle population; then W
-warm-up frames, then exactly K timed frames.
+The default workload is the stress scene, the largest one that runs on one
+GPU: FFT 4096^2 over 8 km, 64 patches of 128^2 to 1024^2 cells at 0.25 m
+following their own moving sources, 16 buckets (wavelengths 0.25-64 m),
+about 15.5M live particles.  The scene is first pre-rolled (untimed) to
+frame 900 of its 1000-frame run so the timed frames see the steady particle
+population; then W warm-up frames, then exactly K timed frames.
 
 Printed: one JSON line.  `value` is ms per frame of the production form
 (16-byte records, all patches per launch, frame replayed as a hipGraph);
 the plain form (32-byte records, launches per patch, no graph) is timed on
 the same frames and reported beside it.  `roofline` is for the kernel with
 the largest share of the frame, timed with HIP events on the library stream;
+`error` is the height error of both forms at the last timed frame against
+the FP64 oracle (background, raw and blended maps of every patch);
 `cpu_baseline` is the FP64 oracle on a bounded sample of the same frames.
 """
 from __future__ import annotations
@@ -190,7 +193,49 @@ def cpu_baseline(scene, preroll, nframes):
         for p in range(len(scene.patches)):
             o.patch_maps(p, H)
     dt = time.perf_counter() - t0
+    o.close()
     return dt * 1e3 / nframes, dt
+
+
+def oracle_frame(scene, n, P):
+    """One full frame of the FP64 oracle (one thread) on a large scene,
+    started from the particle state after step n given as records P (the
+    library's state, whose integer part equals the oracle's own bit for bit
+    in the full-length parity tests): the background and both maps of every
+    patch at step n, then the bookkeeping of step n + 1.  Returns the time,
+    the background and the (raw, blended) maps of step n."""
+    import oracle
+    o = oracle.Oracle(scene)
+    o.load(n, P)
+    t0 = time.perf_counter()
+    H = o.background()
+    maps = [o.patch_maps(p, H) for p in range(len(scene.patches))]
+    o.step(1)
+    dt = time.perf_counter() - t0
+    o.close()
+    return dt, H, maps
+
+
+def rel_rms(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.sqrt(np.mean((a - b) ** 2)) / max(np.sqrt(np.mean(b ** 2)), 1e-300))
+
+
+def height_errors(ocean, scene, H, maps):
+    """Height error of a GPU frame against the FP64 oracle, per result:
+    background, raw wave-particle map and blended map; relative RMS (the
+    largest over patches for the maps) and the largest absolute error (m)."""
+    gh = ocean.background()
+    out = {"background": {"rel_rms": rel_rms(gh, H), "max_abs": float(np.max(np.abs(gh - H)))}}
+    for name, layer, k in (("raw", 1, 0), ("blended", 0, 1)):
+        rr = ma = 0.0
+        for p in range(len(scene.patches)):
+            gm = ocean.patch_map(p, layer)
+            rr = max(rr, rel_rms(gm, maps[p][k]))
+            ma = max(ma, float(np.max(np.abs(gm - maps[p][k]))))
+        out[name] = {"rel_rms": rr, "max_abs": ma}
+    return {k: {kk: float(f"{vv:.3e}") for kk, vv in v.items()} for k, v in out.items()}
 
 
 def bins_for(ocean, scene):
@@ -247,9 +292,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=60)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c5")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-error", action="store_true",
+                    help="skip the height error against the FP64 oracle")
     ap.add_argument("--cpu-frames", type=int, default=0)
     ap.add_argument("--trends", action="store_true",
                     help="paper-default scene over wind speeds and sampling densities (Table 2 trends)")
@@ -301,6 +348,26 @@ def main():
         spin(gp, W)
         plain_ms = time_frames(gp, K)
         log(f"[bench] plain form {plain_ms:.4f} ms/frame")
+
+    # ---- the FP64 oracle on the last timed frame: height error of both
+    #      forms, and (large scenes) the oracle's time for one full frame
+    n_end = preroll + W + K
+    big = len(scene.patches) > 1 or preroll > 1000
+    error = frame_sec = None
+    if not (args.no_error and (args.no_cpu or not big)):
+        P = g.particles()
+        frame_sec, H_o, maps_o = oracle_frame(scene, n_end, P)
+        del P
+        if not args.no_error:
+            error = {"frame": n_end, "patches": len(scene.patches), "tolerance_rel_rms": 1e-4,
+                     "oracle": "FP64 background and maps of every patch at that frame, from the library's "
+                               "particle state (integer state equal to the oracle's, full-length parity tests)",
+                     "production": height_errors(g, scene, H_o, maps_o)}
+            if plain_ms is not None:
+                error["plain_fp32"] = height_errors(gp, scene, H_o, maps_o)
+            log(f"[bench] height error vs FP64 oracle at frame {n_end}: {error['production']}")
+        del H_o, maps_o
+    if plain_ms is not None:
         gp.close()
 
     # ---- per-kernel times with HIP events on the library stream (same frames)
@@ -393,13 +460,21 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        nf = args.cpu_frames or (200 if args.config in ("c1", "c2", "c4") else 1)
-        cms, csec = cpu_baseline(scene, preroll + W, nf)
-        cpu = {"value": round(cms, 3), "unit": "ms/frame", "cores": 1, "kind": "oracle",
-               "sample": f"{nf} full frames (bookkeeping, FP64 FFT background, splat and blend of every "
-                         f"patch) after frame {preroll + W}; {csec:.1f} s; one thread of {os.cpu_count()} "
-                         f"({cpu_model()})"}
-        log(f"[bench] oracle {cms:.1f} ms/frame over {nf} frames")
+        if big and frame_sec is not None:
+            cpu = {"value": round(frame_sec * 1e3, 3), "unit": "ms/frame", "cores": 1, "kind": "oracle",
+                   "sample": f"one full frame (FP64 FFT background, splat and blend of all "
+                             f"{len(scene.patches)} patches at frame {n_end}, then the bookkeeping of frame "
+                             f"{n_end + 1}), started from the particle state of frame {n_end}; "
+                             f"{frame_sec:.1f} s; one thread of {os.cpu_count()} ({cpu_model()})"}
+            log(f"[bench] oracle {frame_sec * 1e3:.1f} ms/frame (one frame)")
+        else:
+            nf = args.cpu_frames or 200
+            cms, csec = cpu_baseline(scene, preroll + W, nf)
+            cpu = {"value": round(cms, 3), "unit": "ms/frame", "cores": 1, "kind": "oracle",
+                   "sample": f"{nf} full frames (bookkeeping, FP64 FFT background, splat and blend of every "
+                             f"patch) after frame {preroll + W}; {csec:.1f} s; one thread of {os.cpu_count()} "
+                             f"({cpu_model()})"}
+            log(f"[bench] oracle {cms:.1f} ms/frame over {nf} frames")
 
     out = {
         "metric": METRIC,
@@ -431,6 +506,7 @@ def main():
         "kernel_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "error": error,
     }
     print(json.dumps(out), flush=True)
 

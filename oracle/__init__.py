@@ -90,6 +90,7 @@ def lib():
         "orc_set_h0": (C.c_int, [vp, P(dbl), P(dbl)]),
         "orc_splat": (C.c_int, [vp, i32, P(i64), i64, P(dbl)]),
         "orc_seek": (C.c_int, [vp, i64]),
+        "orc_load": (C.c_int, [vp, i64, P(i64), i64]),
         "orc_blend": (C.c_int, [vp, i32, P(dbl), P(dbl), P(dbl)]),
     }
     for name, (res, args) in sig.items():
@@ -332,6 +333,14 @@ class Oracle:
         """Step index n (with its windows) for evaluating caller-supplied
         particles and maps; only for an oracle that holds no particles."""
         self._check(self.L.orc_seek(self.h, int(n)))
+
+    def load(self, n: int, recs: np.ndarray):
+        """Take caller-supplied particle records (the ten-column layout of
+        ``particles()``) as the state after step n; the next ``step``
+        continues from there.  Used to time one full frame of a large scene
+        without re-running its history."""
+        r = np.ascontiguousarray(recs, dtype=np.int64).reshape(-1, 10)
+        self._check(self.L.orc_load(self.h, int(n), _p(r, C.c_int64), r.shape[0]))
 
     def blend(self, p: int, H: np.ndarray, raw: np.ndarray) -> np.ndarray:
         H = np.ascontiguousarray(H, dtype=np.float64)

@@ -1390,6 +1390,46 @@ int orc_sample_probes(orc_ocean *o, const double *H, const double *B, const doub
 
 /* Splat caller-placed particles (canonical records) into a patch map at the
  * current step; used by the closed-form pins. */
+/* Replace the particle state by caller-supplied records (ten integer
+ * columns, the layout of orc_particles) as the state after step n, with the
+ * windows and bin histograms of that step; the counters are left as they
+ * are.  Test infrastructure for timing a full frame of a large scene without
+ * re-running its whole history: the next orc_step continues from step n. */
+int orc_load(orc_ocean *o, int64_t n, const int64_t *recs, int64_t count) {
+    if (!o->have_spec) return fail(o, "set_spectrum first");
+    if (n < 0 || count < 0) return fail(o, "step and count must be >= 0");
+    prt_t *P = (prt_t *)malloc(sizeof(prt_t) * (size_t)(count > 0 ? count : 1));
+    if (!P) return fail(o, "out of memory");
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t *d = recs + 10 * k;
+        prt_t *q = &P[k];
+        q->patch = (int32_t)d[0];
+        q->bucket = (int32_t)d[1];
+        q->kind = (int32_t)d[2];
+        q->level = (int32_t)d[3];
+        q->code = (int32_t)d[4];
+        q->birth = d[5];
+        q->ox = d[6];
+        q->oy = d[7];
+        q->src = (int32_t)d[8];
+        q->slot = (int32_t)d[9];
+        if (q->patch < 0 || q->patch >= o->np || q->bucket < 0 || q->bucket >= o->nb || q->code < 0 ||
+            q->code >= NCODE || q->birth > n || (q->kind == 1 && (q->src < 0 || q->src >= o->ns))) {
+            free(P);
+            return fail(o, "record out of range");
+        }
+    }
+    free(o->P);
+    o->P = P;
+    o->nP = count;
+    o->capP = count > 0 ? count : 1;
+    o->n = n;
+    o->stepped = 1;
+    update_windows(o, n);
+    rebuild_hist(o);
+    return 0;
+}
+
 int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *raw) {
     if (p < 0 || p >= o->np) return fail(o, "patch out of range");
     const patch_t *pt = &o->pt[p];

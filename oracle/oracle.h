@@ -90,6 +90,8 @@ int orc_splat(orc_ocean *o, int32_t patch, const int64_t *recs, int64_t n, doubl
 /* Step index n (and its windows) for an oracle without particles: evaluation
  * of caller-supplied particles and maps at that step. */
 int orc_seek(orc_ocean *o, int64_t n);
+/* particle state after step n from caller records (orc_particles layout); test infrastructure */
+int orc_load(orc_ocean *o, int64_t n, const int64_t *recs, int64_t count);
 /* Blend of a caller-supplied raw patch map with background H at the current step. */
 int orc_blend(orc_ocean *o, int32_t patch, const double *H, const double *raw, double *blended);
 
