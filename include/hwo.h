@@ -248,6 +248,20 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
  * the first step; n at most 2^24.  Syncs. */
 int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int32_t on_device);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the probe
+ * sampling of hwo_sample_probes with host arrays xy (n x 2 doubles, world
+ * metres) and out (n x 4 floats: height, unit normal), staged through a
+ * static device array of 4 MiB that each GPU holds until the process ends;
+ * this call allocates nothing.  n at most 131072 (HWO_ERANGE above),
+ * HWO_ESTATE before the first step (it never builds the device state,
+ * which allocates), HWO_EDEVICE if the array's address could not be looked
+ * up when the spectrum was set.  Every handle on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (from several threads or streams)
+ * race; consecutive calls do not, since each synchronises the stream before
+ * it returns.  The caller owns xy and out. */
+int hwo_sample_probes_static(hwo_ocean *o, const double *xy, int64_t n, float *out);
+
 /* Checkpoint and resume of the pipeline state (Sec 4.1, Fig 3: the state
  * one frame hands to the next).  A snapshot is a host-memory image of the
  * state at the current step boundary (step index, counters, bin offsets, live

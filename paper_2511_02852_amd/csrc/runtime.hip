@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -92,6 +93,9 @@ struct hwo_ocean {
   // device
   hipStream_t st = nullptr;
   bool own_stream = false;
+  int device = 0;                  // device current when the stream was set up
+  void *scratch = nullptr;         // that device's static probe staging (see probe_scratch)
+  std::string scratch_err;         // why the scratch address could not be had, if so
   Dev dev{};
   std::vector<void *> allocs;
   float2 *h0T = nullptr, *tw = nullptr;
@@ -151,6 +155,36 @@ struct hwo_ocean {
     hipError_t e_ = (expr);                               \
     if (e_ != hipSuccess) return o->hip_fail(e_, #expr);  \
   } while (0)
+
+// ---------------------------------------------------------------- static scratch
+// Staging memory of hwo_sample_probes_static, for callers that cannot
+// allocate: probe positions in the first half, results in the second.  Each
+// GPU holds its own copy of this array for the life of the process; its
+// address on a device comes from hipGetSymbolAddress with that device
+// current (the array's name is not a device address in host code).  Every
+// handle on one GPU shares that GPU's copy.
+constexpr size_t kScratchBytes = (size_t)4 << 20;
+constexpr int64_t kScratchProbes = (int64_t)(kScratchBytes / 2 / 16);   // 16 B in and 16 B out per probe
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's scratch, looked up once per device.
+static hipError_t probe_scratch(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------- spectrum
 static double jonswap_h(const hwo_ocean *o, double w) {
@@ -357,6 +391,12 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp) {
   } else {
     HWO_CHECK(hipStreamCreateWithFlags(&o->st, hipStreamNonBlocking));
     o->own_stream = true;
+  }
+  HWO_CHECK(hipGetDevice(&o->device));
+  {
+    // only hwo_sample_probes_static needs it; it reports a failure here
+    const hipError_t e = probe_scratch(o->device, &o->scratch);
+    if (e != hipSuccess) o->scratch_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
   }
   const int N = o->cfg.fft_n;
   o->h0T = (float2 *)o->alloc(sizeof(float2) * (size_t)N * N);
@@ -1381,6 +1421,26 @@ int hwo_sample_probes(hwo_ocean *o, const double *xy, int64_t n, float *out, int
   if (txy) (void)hipFree(txy);
   if (tout) (void)hipFree(tout);
   if (e != hipSuccess) return o->hip_fail(e, "sample_probes");
+  return HWO_OK;
+}
+
+int hwo_sample_probes_static(hwo_ocean *o, const double *xy, int64_t n, float *out) {
+  if (!o || n < 0 || (n > 0 && (!xy || !out))) return HWO_EINVAL;
+  if (n > kScratchProbes) return o->fail(HWO_ERANGE, "more probes than the static scratch holds (131072)");
+  // no finalize here: building the device state allocates
+  if (!o->finalized || o->n_host == 0) return o->fail(HWO_ESTATE, "step at least once before sampling");
+  if (!o->scratch) return o->fail(HWO_EDEVICE, "static scratch unavailable: " + o->scratch_err);
+  if (n == 0) return HWO_OK;
+  unsigned char *base = (unsigned char *)o->scratch;
+  void *sxy = base, *sout = base + kScratchBytes / 2;
+  hipError_t e = hipMemcpyAsync(sxy, xy, sizeof(double) * 2 * (size_t)n, hipMemcpyHostToDevice, o->st);
+  if (e == hipSuccess) {
+    launch_probes(o->dev, sxy, (int)n, sout, o->st);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(out, sout, sizeof(float) * 4 * (size_t)n, hipMemcpyDeviceToHost, o->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(o->st);
+  if (e != hipSuccess) return o->hip_fail(e, "sample_probes_static");
   return HWO_OK;
 }
 

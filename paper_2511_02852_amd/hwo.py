@@ -21,7 +21,7 @@ STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "spla
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
-           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes",
+           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes", "hwo_sample_probes_static",
            "hwo_snapshot_size", "hwo_snapshot", "hwo_restore"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -99,6 +99,7 @@ def lib():
         "hwo_time_stage": (C.c_int, [vp, i32, i32, P(C.c_double)]),
         "hwo_record_bytes": (i32, [vp]),
         "hwo_sample_probes": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float), i32]),
+        "hwo_sample_probes_static": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float)]),
         "hwo_snapshot_size": (C.c_int, [vp, P(i64)]),
         "hwo_snapshot": (C.c_int, [vp, vp, i64]),
         "hwo_restore": (C.c_int, [vp, vp, i64]),
