@@ -171,6 +171,42 @@ def copy_bandwidth(mib=512, reps=10):
     return 2.0 * mib * (1 << 20) / (ms * 1e-3) / 1e9
 
 
+def splat_bucket_report(prof, splat_ms, ocean, scene, rec_bytes):
+    """Per-bucket time of the splat from its in-kernel profile and the
+    binding roof of each bucket.  A bucket's time is its share of the
+    wavefront ticks (its footprints plus its share of record decoding, by
+    points visited) times the splat's time per launch; its algorithmic work
+    is its records read once (bytes) and two flops per cell of every crest
+    and trough footprint (2 r / dx)^2 (FP32 matrix flops); the binding roof
+    is the one whose floor time is larger, and frac = floor / time."""
+    nb = scene.spectrum.n_buckets
+    r = ocean.buckets()[:, 2]
+    live = np.zeros(nb)
+    area = np.zeros(nb)
+    for p, P in enumerate(scene.patches):
+        c = ocean.counts(p, allow_overflow=True)[:, 0]
+        live += c
+        area += c * (2.0 * r / P.dx) ** 2
+    bt, pts = prof["bucket"], prof["points"]
+    over = prof["setup"] + prof["wait"] + prof["epilogue"]
+    tot = over + prof["decode"] + bt.sum()
+    rows = []
+    for b in range(nb):
+        share = (bt[b] + prof["decode"] * pts[b] / max(pts.sum(), 1.0)) / tot
+        t = share * splat_ms * 1e-3
+        byts = live[b] * rec_bytes
+        flops = 2.0 * 2.0 * area[b]
+        t_hbm, t_mfma = byts / (HBM_PEAK_GBS * 1e9), flops / (FP32_PEAK_TFLOPS * 1e12)
+        bound = "mfma" if t_mfma > t_hbm else "hbm"
+        rows.append({"bucket": b, "r_cells": round(float(r[b] / min(P.dx for P in scene.patches)), 2),
+                     "live": int(live[b]), "points_visited_per_launch": int(pts[b]),
+                     "share": round(float(share), 4), "ms": round(t * 1e3, 5), "bound": bound,
+                     "frac": round(max(t_hbm, t_mfma) / t, 5) if t > 0 else None})
+    return {"buckets": rows,
+            "overhead_share": {k: round(float(prof[k] / tot), 4) for k in ("setup", "wait", "epilogue")},
+            "decode_share": round(float(prof["decode"] / tot), 4)}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -387,7 +423,17 @@ def main():
     rep = ("fft_a", "fft_b", "deposit_x", "filter_y", "layer_sum") if layers else \
         ("fft_a", "fft_b", "splat", "splat_plan", "splat_reduce")
     rep_ms = {k: gt.time_stage(k, 20) for k in rep}
-    gt.close()
+    prof = None
+    if not layers:
+        # in-kernel per-bucket profile of the splat over K more frames
+        gt.set_splat_profile(True)
+        gt.step(K)
+        gt.sync()
+        prof = gt.splat_profile()
+        gt.set_splat_profile(False)
+        prof_live = gt
+    else:
+        gt.close()
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in st.items()}
     per_launch.update(rep_ms)
     per_frame = {k: v[0] / K for k, v in st.items()}
@@ -402,6 +448,12 @@ def main():
     splat_ms = (per_launch["deposit_x"] + per_launch["filter_y"] + per_launch["layer_sum"]) if layers \
         else per_launch["splat"]
     splats_per_s = live_t / (splat_ms * 1e-3) if splat_ms > 0 else None
+    splat_buckets = None
+    if prof is not None:
+        splat_buckets = splat_bucket_report(prof, per_launch["splat"], prof_live, scene, g.record_bytes)
+        prof_live.close()
+        log("[bench] splat per bucket (share, frac of binding roof): " +
+            ", ".join(f"b{r['bucket']}={r['share']:.3f}/{r['frac']}" for r in splat_buckets["buckets"]))
 
     # dominant kernel (largest time share) and its roofline: the roof whose
     # floor time (algorithmic bytes / 8 TB/s or flops / FP32 matrix peak) is
@@ -505,6 +557,7 @@ def main():
         "copy_gbps": round(copy_gbs, 1),
         "kernel_ms_per_launch": {k: round(v, 5) for k, v in per_launch.items()},
         "roofline": roofline,
+        "splat_per_bucket": splat_buckets,
         "cpu_baseline": cpu,
         "error": error,
     }

@@ -291,6 +291,22 @@ int hwo_restore(hwo_ocean *o, const void *src, int64_t src_bytes);
  *   pairs.  Stages 6-8 run with synth 0, stages 10-12 with synth 1. */
 int hwo_set_timing(hwo_ocean *o, int32_t enable);
 int hwo_stage_times(hwo_ocean *o, double *ms, int64_t *launches, int32_t n);
+/* Per-bucket profile of the splat (Sec 4.2: the per-bucket layers of
+ * Fig 1's crest/trough pairs), for attributing its time.  With enable = 1
+ * the splat runs as a profiling instance of its kernel in which each
+ * wavefront reads the shader clock (s_memtime) at the boundaries of its work
+ * and adds the ticks since its previous mark to a category; enable 0 returns
+ * to the plain instance (a change re-captures the frame graph); the
+ * accumulators are cleared by every call.  hwo_read_splat_profile copies the 36 accumulators
+ * into dst (n >= 36), as doubles: [0] item set-up, [1] record decode,
+ * [2] end-of-chunk wait, [3] epilogue (blend or partial tile), [4 + b]
+ * footprints of bucket b, [20 + b] crest and trough points of bucket b
+ * visited (b < 16).  Ticks are summed over wavefronts, so only their
+ * shares are meaningful; the marks themselves cost a little time.
+ * HWO_EINVAL for a bad argument, HWO_ESTATE (read) before the device state
+ * exists.  Both synchronise the stream. */
+int hwo_set_splat_profile(hwo_ocean *o, int32_t enable);
+int hwo_read_splat_profile(hwo_ocean *o, double *dst, int32_t n);
 /* Benchmark support (Sec 5.2 frame-time measurements): after at least one
  * step, launch the kernels of one
  * stage reps times back to back between two HIP events on the library stream

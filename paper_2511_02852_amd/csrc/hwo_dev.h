@@ -117,6 +117,18 @@ struct Globals {
   int32_t pad;
 };
 
+// Per-bucket splat profile (wavefront clock ticks of s_memtime, summed over
+// wavefronts; points visited): categories of a work item's time.
+enum {
+  PROF_SETUP = 0,    // item set-up: row tables, prefix of the lists, part shares
+  PROF_DECODE = 1,   // records decoded into crest/trough points (and the barrier after)
+  PROF_WAIT = 2,     // end-of-chunk barrier: waiting for the other wavefronts
+  PROF_EPILOGUE = 3, // quadrants into the tile, blend or partial tile store
+  PROF_BUCKET = 4,   // + b: footprints of bucket b
+  PROF_POINTS = PROF_BUCKET + kMaxBuckets,   // + b: crest and trough points of bucket b visited
+  PROF_N = PROF_POINTS + kMaxBuckets
+};
+
 enum { CNT_INJ = 0, CNT_EMIT, CNT_SUB, CNT_DIED, CNT_NUM };
 
 // Everything a kernel needs, passed by value.
@@ -138,6 +150,7 @@ struct Dev {
   const float *bucket_r;       // [nb] radius (m)
   const int32_t *margin;       // [nb] ceil(2 r 2^20)
   const float *ring_m;         // [sum ne] ring multipliers
+  const float *ring_amp;       // [ns][kMaxRing] ring amplitude B m of each slot before subdivision
   const int2 *ring_O;          // [sum ne] ring offsets (units)
   Globals *glob;
   StepPatch *sp;
@@ -182,6 +195,8 @@ struct Dev {
   const int2 *toff;            // [nb][kNCode] trough offset round(r (cos, sin) 2^20)
   int32_t lsmem;               // dynamic LDS bytes of the layer passes
   float *nrm;                  // [3][ncells] unit normals (x, y, z planes); null unless enabled
+  unsigned long long *splat_prof;   // [PROF_N] per-bucket splat profile
+  int32_t splat_profile;            // 1: launch the profiling instance of the splat
 };
 
 // ---------------------------------------------------------------- helpers
@@ -268,8 +283,10 @@ __device__ inline float particle_amp(const Dev &d, const Part &p) {
   if (m_kind(m) == 0)
     return d.patches[m_patch(m)].A[m_bucket(m)] * (d.afac ? d.afac[m_bucket(m) * kNCode + p.code] : 1.f);
   const SourceDev &s = d.sources[m_src(m)];
-  const float inv3[5] = {1.f, 1.f / 3.f, 1.f / 9.f, 1.f / 27.f, 1.f / 81.f};
-  return s.B * d.ring_m[s.ring0 + m_slot(m)] * inv3[m_level(m)];
+  // 3^-level, each constant correctly rounded (a select chain, not a local array)
+  const uint32_t lv = m_level(m);
+  const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;
+  return s.B * d.ring_m[s.ring0 + m_slot(m)] * inv3;
 }
 
 // ---------------------------------------------------------------- output tiles

@@ -88,6 +88,7 @@ struct hwo_ocean {
   std::vector<PatchDev> pdev;
   std::vector<SourceDev> sdev;
   std::vector<float> ring_m;
+  std::vector<float> ring_amp;     // [ns][kMaxRing] B_s m_s[j] (FP32 product, as on the device)
   std::vector<int2> ring_O;
   std::vector<int32_t> src_order;
   // device
@@ -571,6 +572,7 @@ static int build_scene_tables(hwo_ocean *o) {
   }
   o->sdev.assign(ns, SourceDev{});
   o->ring_m.clear();
+  o->ring_amp.assign((size_t)std::max(ns, 1) * kMaxRing, 0.f);
   o->ring_O.clear();
   for (int si = 0; si < ns; ++si) {
     const hwo_source &hs = o->sources[si];
@@ -609,6 +611,8 @@ static int build_scene_tables(hwo_ocean *o) {
       S.E = 0;
       S.B = 0.f;
     }
+    for (int j = 0; j < hs.ring_n; ++j)
+      o->ring_amp[(size_t)si * kMaxRing + j] = S.B * o->ring_m[(size_t)S.ring0 + j];
     for (int L = 0; L < kMaxLevel; ++L) {
       const double alpha = 2.0 * M_PI / ((double)hs.ring_n * (double)ipow3(L));
       const double x = (o->sp.subdiv_frac * rb / alpha - R) / (cb * dt);
@@ -701,6 +705,7 @@ static int finalize(hwo_ocean *o) {
   d.bucket_r = upload(o, br, &rc);
   d.margin = upload(o, bm, &rc);
   d.ring_m = upload(o, o->ring_m, &rc);
+  d.ring_amp = upload(o, o->ring_amp, &rc);
   d.ring_O = upload(o, o->ring_O, &rc);
   if (rc) return rc;
   int64_t cells = 0;
@@ -824,6 +829,9 @@ static int finalize(hwo_ocean *o) {
       !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
     return o->fail(HWO_ENOMEM, "device allocation failed");
   HWO_CHECK(hipMemsetAsync(d.glob, 0, sizeof(Globals), o->st));
+  d.splat_prof = (unsigned long long *)o->alloc(sizeof(unsigned long long) * PROF_N);
+  if (!d.splat_prof) return o->fail(HWO_ENOMEM, "device allocation failed");
+  HWO_CHECK(hipMemsetAsync(d.splat_prof, 0, sizeof(unsigned long long) * PROF_N, o->st));
   HWO_CHECK(hipMemsetAsync(d.sp, 0, sizeof(StepPatch) * std::max(np, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.ctr, 0, sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.hist, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
@@ -1453,6 +1461,36 @@ int hwo_set_timing(hwo_ocean *o, int32_t enable) {
     o->stage_ms[s] = 0.0;
     o->stage_n[s] = 0;
   }
+  return HWO_OK;
+}
+
+int hwo_set_splat_profile(hwo_ocean *o, int32_t enable) {
+  if (!o || (enable != 0 && enable != 1)) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  Dev &d = o->dev;
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  HWO_CHECK(hipMemsetAsync(d.splat_prof, 0, sizeof(unsigned long long) * PROF_N, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  if (d.splat_profile != enable) {
+    // the profiling splat is another kernel instance: capture the frame again
+    d.splat_profile = enable;
+    if (o->exec) (void)hipGraphExecDestroy(o->exec);
+    if (o->graph) (void)hipGraphDestroy(o->graph);
+    o->exec = nullptr;
+    o->graph = nullptr;
+  }
+  return HWO_OK;
+}
+
+int hwo_read_splat_profile(hwo_ocean *o, double *dst, int32_t n) {
+  if (!o || !dst || n < PROF_N) return HWO_EINVAL;
+  if (!o->finalized) return o->fail(HWO_ESTATE, "no profile before the device state exists");
+  const Dev &d = o->dev;
+  unsigned long long h[PROF_N];
+  HWO_CHECK(hipMemcpyAsync(h, d.splat_prof, sizeof(h), hipMemcpyDeviceToHost, o->st));
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  for (int i = 0; i < PROF_N; ++i) dst[i] = (double)h[i];
   return HWO_OK;
 }
 

@@ -45,7 +45,10 @@ namespace hwo {
 
 namespace {
 
-constexpr int kPad = kTile + 1;
+// Row stride of the LDS tile: 72 words puts the 8 x 8 cells of a small bin on
+// distinct banks (bank = 8 row + column), where the small-footprint atomics of
+// a wavefront (points sorted by bin) cluster.
+constexpr int kPad = kTile + 8;
 
 // Raised cosine w(t r) for t = d / r: cos^2(pi t / 2) on |t| < 1, else 0.
 // v_cos_f32 takes its argument in revolutions: cos(pi t / 2) = cos(2 pi t / 4).
@@ -53,23 +56,6 @@ constexpr int kPad = kTile + 1;
 __device__ __forceinline__ float wrev(float q) {
   const float c = __builtin_amdgcn_cosf(q);
   return (fabsf(q) < 0.25f) ? c * c : 0.f;
-}
-
-// Decode a particle record: crest centre in tile cell coordinates, amplitude, direction.
-template <class Rec>
-__device__ __forceinline__ bool load_item(const Dev &d, const Rec &r, int64_t n, int b, const TileGeom &T, float &cx,
-                                          float &cy, float &A, float2 &u) {
-  const Part q = RecIO<Rec>::unpack(r, n);
-  if ((int)m_bucket(q.meta) != b || (int)m_patch(q.meta) != T.p) return false;
-  const int2 v = d.V[b * kNCode + q.code];
-  const int64_t px = (int64_t)q.ox + (((int64_t)q.age * v.x) >> 12);
-  const int64_t py = (int64_t)q.oy + (((int64_t)q.age * v.y) >> 12);
-  cx = (float)(px - T.X0) * T.inv_dxu;
-  cy = (float)(py - T.Y0) * T.inv_dxu;
-  A = (RecIO<Rec>::kHasAmp || m_kind(q.meta) != 0) ? particle_amp<Rec>(d, q)
-                                                    : T.Ab * (d.afac ? d.afac[b * kNCode + q.code] : 1.f);
-  u = d.UC[q.code];
-  return true;
 }
 
 }  // namespace
@@ -80,10 +66,16 @@ __device__ __forceinline__ bool load_item(const Dev &d, const Rec &r, int64_t n,
 // per-lane atomics with 4 or 8 cells per axis, or the matrix-core quadrants.
 // Ratios fitted to measured item times (about 1 : 2 : 3.5).
 constexpr uint32_t kCostSmall4 = 4, kCostSmall8 = 8, kCostMatrix = 14;
+// Footprints of at most this many cells per axis go through LDS atomics;
+// larger ones through the matrix cores.  An LDS float atomic costs about one
+// lane per clock of the CU's LDS, so from about 20 cells per footprint on
+// the outer products (one weight per lane per point and quadrant plus half
+// a 32x32x2 product) are cheaper.
+constexpr int kAtomicSpan = 4;
 
 __device__ __forceinline__ uint32_t visit_cost(float rc) {
   const int span = (int)floorf(2.f * rc) + 1;
-  return span <= 3 ? kCostSmall4 : (span <= 7 ? kCostSmall8 : kCostMatrix);
+  return span <= 3 ? kCostSmall4 : (span <= kAtomicSpan ? kCostSmall8 : kCostMatrix);
 }
 
 // One wavefront per output tile: estimated splat cost of the tile, the
@@ -348,7 +340,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int
 }
 
 // ---------------------------------------------------------------- splat
-constexpr int kChunk = kThreads;   // particles decoded into LDS per step
 constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
 constexpr int kSplit = 8;          // entries per block when a tile's lists are dealt to its parts
 
@@ -417,36 +408,147 @@ __device__ __forceinline__ void splat_points_radial(float (*acc)[kPad], const fl
   }
 }
 
-// kRadial selects the radial kernel W(|d|); it is a template parameter so
-// that the separable kernel's register allocation does not carry it.
-template <class Rec, bool kRadial>
-// At most 102 registers per lane: five wavefronts per SIMD (five blocks per CU).
-__global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
+// Footprint of radius rc (cells) centred at (x, y) reaches the 32 x 32
+// quadrant with first cell (xq, yq): some cell centre lies within rc on both axes.
+__device__ __forceinline__ bool reaches(float x, float y, float rc, int xq, int yq) {
+  return x - rc < (float)(xq + 31) && x + rc > (float)xq && y - rc < (float)(yq + 31) && y + rc > (float)yq;
+}
+
+// Add a quadrant accumulator (the matrix-core output layout: lane l holds
+// column xq + l % 32 of rows yq + 8 (r / 4) + 4 (l / 32) + r % 4) to the tile.
+__device__ __forceinline__ void flush_quadrant(float (*acc)[kPad], const f32x16 &cq, int xq, int yq, int lane) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = yq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+    atomicAdd(&acc[row][xq + (lane & 31)], cq[r]);
+  }
+}
+
+constexpr int kBatch = 64;   // list entries a wavefront takes at a time, one per lane
+
+// A record's decode in two halves, so that its table loads can be in flight
+// while the wavefront splats the previous batch: dec_load unpacks the record
+// and issues the loads (velocity and unit direction of its code, amplitude
+// factor), dec_point does the arithmetic once they have arrived.
+struct DecIn {
+  int32_t ox, oy, age;
+  int2 v;          // velocity per step of the code (2^-32 m)
+  float2 u;        // unit direction of the code
+  float f;         // amplitude (wide form), ring amplitude B m, or the stratified direction factor
+  uint32_t flags;  // bit 0 valid, bit 1 ring particle, bits 2-4 level
+};
+
+template <class Rec>
+__device__ __forceinline__ DecIn dec_load(const Dev &d, const Rec &r, int64_t n, int b, int patch, bool valid) {
+  DecIn o;
+  o.ox = 0; o.oy = 0; o.age = 0;
+  o.v = make_int2(0, 0);
+  o.u = make_float2(0.f, 0.f);
+  o.f = 1.f;
+  o.flags = 0u;
+  if (!valid) return o;
+  const Part q = RecIO<Rec>::unpack(r, n);
+  if ((int)m_bucket(q.meta) != b || (int)m_patch(q.meta) != patch) return o;
+  const bool ring = m_kind(q.meta) != 0;
+  o.flags = 1u | (ring ? 2u : 0u) | (m_level(q.meta) << 2);
+  o.ox = q.ox;
+  o.oy = q.oy;
+  o.age = q.age;
+  o.v = d.V[b * kNCode + q.code];
+  o.u = d.UC[q.code];
+  if (RecIO<Rec>::kHasAmp) o.f = q.amp;
+  else if (ring) o.f = d.ring_amp[m_src(q.meta) * kMaxRing + m_slot(q.meta)];
+  else if (d.afac) o.f = d.afac[b * kNCode + q.code];
+  return o;
+}
+
+// Crest (cx, cy) in tile cells and signed amplitude A (0: nothing to splat);
+// the trough lies rc u behind the crest.
+template <class Rec>
+__device__ __forceinline__ void dec_point(const DecIn &i, const TileGeom &T, float Ab, float &cx, float &cy,
+                                          float &A) {
+  const int64_t px = (int64_t)i.ox + (((int64_t)i.age * i.v.x) >> 12);
+  const int64_t py = (int64_t)i.oy + (((int64_t)i.age * i.v.y) >> 12);
+  cx = (float)(px - T.X0) * T.inv_dxu;
+  cy = (float)(py - T.Y0) * T.inv_dxu;
+  const uint32_t lv = (i.flags >> 2) & 7u;
+  const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;
+  if (!(i.flags & 1u)) A = 0.f;
+  else if (RecIO<Rec>::kHasAmp) A = i.f;
+  else if (i.flags & 2u) A = i.f * inv3;
+  else A = Ab * i.f;
+}
+
+// Next point of a batch from the wave-uniform masks of crests (0..63) and
+// troughs (64..127) still to do; -1 when both are empty.
+__device__ __forceinline__ int pop_point(uint64_t &m0, uint64_t &m1) {
+  const bool c = m0 != 0ull;
+  const uint64_t m = c ? m0 : m1;
+  const int kk = m ? __builtin_ctzll(m) + (c ? 0 : kBatch) : -1;
+  const uint64_t rest = m & (m - 1ull);
+  m0 = c ? rest : m0;
+  m1 = c ? m1 : rest;
+  return kk;
+}
+
+// kRadial selects the radial kernel W(|d|) and kProf the per-bucket profile;
+// both are template parameters so that the default instance carries neither.
+// Each work item (one part of one output tile) is processed as follows.  The
+// block loads the bin rows of every bucket that reach the tile and cuts each
+// bucket's list (this part's share) into batches of 64 entries.  Wavefronts
+// then take batches from a counter in LDS, largest buckets first, and work
+// independently: every lane loads and decodes one record (the next batch's
+// records are loaded while the current one is splatted) into a crest and a
+// trough point, and the batch goes through one of two paths into the LDS
+// tile:
+//   * footprints of at most 7 cells per axis: each lane adds its two points
+//     cell by cell with LDS float atomics, weights in registers;
+//   * larger footprints: for each 32 x 32 quadrant of the tile that some of
+//     the batch's points reach, the points (read from their lanes'
+//     registers) are fed two at a time to a 32x32x2 FP32 matrix-core product
+//     (rank-2 update W_y^T (A W_x), each lane computing the one row and one
+//     column weight it supplies) into the wavefront's accumulator of that
+//     quadrant, which stays in registers until the item is done.
+// There is no barrier between batches, so no wavefront waits for another
+// until the item's list is exhausted.
+template <class Rec, bool kRadial, bool kProf>
+// At most 168 registers per lane (the four quadrant accumulators take 64):
+// three wavefronts per SIMD (three blocks per CU).
+__global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, const Rec *__restrict__ direct,
                                                     int ndirect, float *__restrict__ raw_out,
                                                     float *__restrict__ blend_out, int64_t out_off) {
-  __shared__ float acc[kTile][kPad];
-  // decoded chunk: for particle i of the chunk, pt[2i] is its crest and
-  // pt[2i + 1] its trough: centre (tile cells), signed amplitude (0: skip)
-  __shared__ float4 pt[2 * kChunk];
+  __shared__ __align__(16) float acc[kTile][kPad];
   // per bucket: bin rows reaching the tile (start, exclusive prefix of lengths)
   __shared__ int s_rlo[kMaxBuckets][kMaxRows];
   __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
   __shared__ int s_nrows[kMaxBuckets];
-  __shared__ int s_bstart[kMaxBuckets];      // first block of this part in the bucket's list
-  __shared__ int s_boff[kMaxBuckets + 1];    // offsets of the buckets in the item's list
+  __shared__ int s_cnt[kMaxBuckets];          // entries of this part in each bucket's list
+  __shared__ int s_bat[kMaxBuckets + 1];      // first batch of the j-th bucket taken (bucket nb - 1 - j)
   __shared__ int s_tile, s_part, s_nparts, s_patch;
+  __shared__ unsigned long long s_prof[kProf ? PROF_N : 1];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  constexpr int nwaves = kThreads / 64;
   const int64_t n = d.glob->n;
   const Rec *__restrict__ S = direct ? direct : (const Rec *)((n & 1) ? d.S1 : d.S0);
   const int total = direct ? nt : d.splat_ctl[1];
   const int nb = d.nb;
-  // matrix-core path: wavefront w owns the 32 x 32 quadrant (xq, yq) of the tile
-  const int xq = 32 * (wave & 1), yq = 32 * (wave >> 1);
+  // profile: each wavefront charges the clock ticks since its last mark to a
+  // category (the wait for the clock read also drains its LDS operations, so
+  // a batch's atomics are charged to its bucket)
+  uint64_t t_mark = 0;
+  auto mark = [&](int cat) {
+    if constexpr (kProf) {
+      const uint64_t now = __builtin_amdgcn_s_memtime();
+      if (lane == 0) atomicAdd(&s_prof[cat], (unsigned long long)(now - t_mark));
+      t_mark = now;
+    }
+  };
+  if constexpr (kProf)
+    for (int i = tid; i < PROF_N; i += kThreads) s_prof[i] = 0ull;
 
   for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
+    if constexpr (kProf) t_mark = __builtin_amdgcn_s_memtime();
     if (tid == 0) {
       const int4 e = direct ? make_int4(t0 + item, 0, 1, d.tile_patch[t0 + item]) : d.item_desc[item];
       s_tile = e.x;
@@ -454,7 +556,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
       s_nparts = e.z;
       s_patch = e.w;
     }
-    for (int c = tid; c < kTile * kPad; c += kThreads) (&acc[0][0])[c] = 0.f;
+    for (int c = tid; c < kTile * kPad / 4; c += kThreads)
+      reinterpret_cast<float4 *>(&acc[0][0])[c] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     const int tile = s_tile, part = s_part, nparts = s_nparts;
     TileGeom T;
@@ -484,7 +587,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
     }
     __syncthreads();
     // exclusive prefix of the row lengths, one bucket per wave
-    for (int b = wave; b < nb; b += nwaves) {
+    for (int b = wave; b < nb; b += kThreads / 64) {
       const int nrows = s_nrows[b];
       const int len = lane < nrows ? s_pre[b][lane] : 0;
       int inc = len;
@@ -496,180 +599,205 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
       if (lane == 63) s_pre[b][nrows] = inc;
     }
     __syncthreads();
-    if (tid == 0) {
-      int accum = 0;
-      for (int b = 0; b < nb; ++b) {
+    if (wave == 0) {
+      // lane j: the j-th bucket in processing order (largest radii first)
+      int cnt = 0;
+      if (lane < nb) {
+        const int b = nb - 1 - lane;
         const int M = s_pre[b][s_nrows[b]];
         // blocks part, part + nparts, ... of kSplit entries; the last block may be short
         const int nblk = (M + kSplit - 1) / kSplit;
-        int cnt = nblk > part ? (nblk - part + nparts - 1) / nparts * kSplit : 0;
+        cnt = nblk > part ? (nblk - part + nparts - 1) / nparts * kSplit : 0;
         if (nblk > 0 && (nblk - 1) % nparts == part) cnt -= nblk * kSplit - M;
-        s_bstart[b] = part;
-        s_boff[b] = accum;
-        accum += cnt;
+        s_cnt[b] = cnt;
       }
-      s_boff[nb] = accum;
+      const int nbj = (cnt + kBatch - 1) / kBatch;
+      int inc = nbj;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+      }
+      if (lane < nb) s_bat[lane] = inc - nbj;
+      if (lane == nb - 1) s_bat[nb] = inc;
     }
     __syncthreads();
-    const int Mi = s_boff[nb];
-    const bool quad_live = xq < T.tw && yq < T.th;
-    f32x16 cq;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) cq[r] = 0.f;
+    mark(PROF_SETUP);
+    // the batch table in registers (lane j: the j-th bucket taken), so that
+    // finding a batch's bucket costs no LDS access
+    const int bat_lo = lane < nb ? s_bat[lane] : 0x7FFFFFFF;
+    const int bat_cnt = lane < nb ? s_cnt[nb - 1 - lane] : 0;
+    const int nbat = s_bat[nb];
     const uint64_t t_work = __builtin_amdgcn_s_memrealtime();   // 100 MHz
 
-    // The records of chunk c + 1 are loaded while chunk c is splatted.
-    Rec rec;
-    int rec_b = -1;   // bucket of the prefetched record, -1: none
-    auto fetch = [&](int c) {
-      rec_b = -1;
-      if (tid < min(kChunk, Mi - c)) {
-        // item-list index -> bucket -> bin row -> particle
-        const int g = c + tid;
-        int b = 0;
-        while (b + 1 < nb && s_boff[b + 1] <= g) ++b;
-        const int gl = g - s_boff[b];
-        const int v = (s_bstart[b] + gl / kSplit * nparts) * kSplit + gl % kSplit;
+    // batch k -> bucket and first entry (wavefront w takes batches w, w + 4, ...)
+    auto locate = [&](int k, int &b, int &cnt) {
+      // j-th bucket taken: the last one whose first batch is at or before k
+      // (a bucket without batches starts where the next one does)
+      const int j = __popcll(__ballot(bat_lo <= k)) - 1;
+      b = nb - 1 - j;
+      const int e0 = (k - __builtin_amdgcn_readlane(bat_lo, j)) * kBatch;
+      cnt = min(kBatch, __builtin_amdgcn_readlane(bat_cnt, j) - e0);
+      return e0;
+    };
+    // the lane's record of a batch: list entry -> this part's block -> bin row -> particle
+    auto fetch = [&](int b, int e0, int cnt, Rec &rec) {
+      if (lane < cnt) {
+        const int gl = e0 + lane;
+        const int v = (part + gl / kSplit * nparts) * kSplit + gl % kSplit;
         int lo = 0, hi = s_nrows[b] - 1;   // last row with prefix <= v
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
         }
         rec = S[s_rlo[b][lo] + (v - s_pre[b][lo])];
-        rec_b = b;
       }
     };
-    fetch(0);
-    for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
-      const int m = min(kChunk, Mi - c);
-      // ---- decode the prefetched records into crest and trough points
-      if (rec_b >= 0) {
-        const int b = rec_b;
-        float cx = 0.f, cy = 0.f, A = 0.f;
-        float2 u = make_float2(0.f, 0.f);
-        TileGeom Tb = T;
-        Tb.Ab = P.A[b];
-        if (!load_item<Rec>(d, rec, n, b, Tb, cx, cy, A, u)) A = 0.f;
-        const float rc = d.bucket_r[b] / (float)P.dx;
-        const float tx = cx - rc * u.x, ty = cy - rc * u.y;
-        // quadrants of the tile a footprint reaches (bit w: quadrant of
-        // wavefront w), used by the matrix-core path
-        auto quads = [&](float x, float y) {
-          if (A == 0.f) return 0u;
-          const bool x0 = x - rc < 31.f && x + rc > 0.f, x1 = x - rc < 63.f && x + rc > 32.f;
-          const bool y0 = y - rc < 31.f && y + rc > 0.f, y1 = y - rc < 63.f && y + rc > 32.f;
-          return (uint32_t)(x0 && y0) | (uint32_t)(x1 && y0) << 1 | (uint32_t)(x0 && y1) << 2 |
-                 (uint32_t)(x1 && y1) << 3;
-        };
-        pt[2 * tid] = make_float4(cx, cy, A, __uint_as_float(quads(cx, cy)));
-        pt[2 * tid + 1] = make_float4(tx, ty, -A, __uint_as_float(quads(tx, ty)));
-      }
-      __syncthreads();
-      if (c + kChunk < Mi) fetch(c + kChunk);
-      // ---- the chunk holds runs of consecutive buckets
-      for (int b = 0; b < nb; ++b) {
-        const int seg_lo = max(c, s_boff[b]) - c, seg_hi = min(c + m, s_boff[b + 1]) - c;
-        if (seg_hi <= seg_lo) continue;   // block-uniform
-        const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
-        const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
-        const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
-        const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
-        if constexpr (kRadial) {
-          // ---- radial kernel: not a sum of outer products, so no matrix cores
-          if (span <= 7) {
-            for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
-              const int q = q0 + lane;
-              const bool valid = q < q_hi;
-              const float4 pv = pt[valid ? q : q_lo];
-              if (span <= 3) splat_points_radial<4>(acc, pv, valid, rc, qs, T.tw, T.th);
-              else splat_points_radial<8>(acc, pv, valid, rc, qs, T.tw, T.th);
-            }
-          } else if (quad_live) {
-            // large footprints: the wavefront's quadrant accumulates in
-            // registers, each lane the 16 cells it holds in the matrix-core
-            // layout (column xq + lane % 32, rows yq + 8 (r / 4) + 4 (lane / 32) + r % 4)
-            const float dxl = (float)(xq + (lane & 31)), ybase = (float)(yq + 4 * (lane >> 5));
-            for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
-              const int q = q0 + lane;
-              const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
-              uint64_t mask = __ballot(hit);
-              while (mask) {   // wave-uniform
-                const float4 pv = pt[q0 + __builtin_ctzll(mask)];
-                mask &= mask - 1;
-                const float dx = dxl - pv.x, dx2 = dx * dx;
+
+    // the wavefront's matrix-core accumulators of the four quadrants, added to
+    // the tile once the item's lists are done
+    f32x16 cq0, cq1, cq2, cq3;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                  const float dy = ybase + (float)(8 * (r >> 2) + (r & 3)) - pv.y;
-                  cq[r] += pv.z * wrev(__builtin_amdgcn_sqrtf(dx2 + dy * dy) * qs);
-                }
-              }
-            }
-          }
-        } else if (span <= 7) {
-          // ---- small footprints: points spread over all wavefronts
-          for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
-            const int q = q0 + lane;
-            const bool valid = q < q_hi;
-            const float4 pv = pt[valid ? q : q_lo];
-            if (span <= 3) splat_points<4>(acc, pv, valid, rc, qs, T.tw, T.th);
-            else splat_points<8>(acc, pv, valid, rc, qs, T.tw, T.th);
-          }
-        } else if (quad_live) {
-          // ---- matrix cores: the wavefront's quadrant gets the rank-2 update
-          //      D += W_y(:, k1 k2) [A_k1 W_x(k1, :); A_k2 W_x(k2, :)]
-          //      for each pair of points that reach it
-          const float yrow = (float)(yq + (lane & 31)), xcol = (float)(xq + (lane & 31));
-          for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
-            const int q = q0 + lane;
-            const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
-            uint64_t mask = __ballot(hit);
-            if (!mask) continue;   // wave-uniform
-            // pairs of hit points; the next pair's point is read from LDS
-            // before the current pair's product is issued
-            auto pop = [&](int &k1, int &k2, float &keep) {
-              k1 = __builtin_ctzll(mask);
-              mask &= mask - 1;
-              k2 = k1;
-              keep = lane < 32 ? 1.f : 0.f;
-              if (mask) {
-                k2 = __builtin_ctzll(mask);
-                mask &= mask - 1;
-                keep = 1.f;
-              }
-            };
-            int k1, k2;
-            float keep;
-            pop(k1, k2, keep);
-            float4 pv = pt[q0 + (lane < 32 ? k1 : k2)];
-            while (true) {
-              const bool more = mask != 0;   // wave-uniform
-              float4 pn = pv;
-              float keep_n = 0.f;
-              if (more) {
-                pop(k1, k2, keep_n);
-                pn = pt[q0 + (lane < 32 ? k1 : k2)];
-              }
-              const float a = wrev((yrow - pv.y) * qs);
-              const float bw = keep * pv.z * wrev((xcol - pv.x) * qs);
-              cq = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bw, cq, 0, 0, 0);
-              if (!more) break;
-              pv = pn;
-              keep = keep_n;
-            }
-          }
-        }
-      }
-      __syncthreads();
+    for (int r = 0; r < 16; ++r) {
+      cq0[r] = 0.f;
+      cq1[r] = 0.f;
+      cq2[r] = 0.f;
+      cq3[r] = 0.f;
     }
-    // ---- matrix-core quadrants into the tile (disjoint per wavefront)
-    if (quad_live) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = yq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        acc[row][xq + (lane & 31)] += cq[r];
+    uint32_t touched = 0;   // quadrants this wavefront's accumulators hold
+    // Three batches are in flight per wavefront: the records of batch k + 2
+    // load while the table loads of batch k + 1 and the splat of batch k run.
+    constexpr int kWaves = kThreads / 64;
+    int k0 = wave, b0 = 0, c0 = 0;
+    Rec r0, r1;
+    if (k0 < nbat) {
+      const int e0 = locate(k0, b0, c0);
+      fetch(b0, e0, c0, r0);
+    }
+    int k1 = wave + kWaves, b1 = 0, c1 = 0;
+    if (k1 < nbat) {
+      const int e0 = locate(k1, b1, c1);
+      fetch(b1, e0, c1, r1);
+    }
+    DecIn in0 = dec_load<Rec>(d, r0, n, b0, T.p, k0 < nbat && lane < c0);
+    while (k0 < nbat) {   // wave-uniform
+      const int k2 = k1 + kWaves;
+      int b2 = 0, c2 = 0;
+      Rec r2;
+      if (k2 < nbat) {
+        const int e0 = locate(k2, b2, c2);
+        fetch(b2, e0, c2, r2);
       }
+      // ---- this batch's points: a crest and a trough per lane
+      const int b = b0;
+      float cx, cy, A;
+      dec_point<Rec>(in0, T, P.A[b], cx, cy, A);
+      const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
+      const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
+      const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
+      const float tx = cx - rc * in0.u.x, ty = cy - rc * in0.u.y;
+      // the next batch's table loads go out before this batch is splatted
+      const DecIn in1 = dec_load<Rec>(d, r1, n, b1, T.p, k1 < nbat && lane < c1);
+      if constexpr (kProf)
+        if (lane == 0) atomicAdd(&s_prof[PROF_POINTS + b], (unsigned long long)(2 * c0));
+      mark(PROF_DECODE);
+      const float4 pc = make_float4(cx, cy, A, 0.f), ptr = make_float4(tx, ty, -A, 0.f);
+      const bool live = A != 0.f;
+      if (span <= kAtomicSpan) {
+        // ---- small footprints: the lane's two points, LDS atomics
+        if constexpr (kRadial) {
+          splat_points_radial<kAtomicSpan>(acc, pc, live, rc, qs, T.tw, T.th);
+          splat_points_radial<kAtomicSpan>(acc, ptr, live, rc, qs, T.tw, T.th);
+        } else {
+          splat_points<kAtomicSpan>(acc, pc, live, rc, qs, T.tw, T.th);
+          splat_points<kAtomicSpan>(acc, ptr, live, rc, qs, T.tw, T.th);
+        }
+      } else {
+        // ---- large footprints: quadrant by quadrant; the points a product
+        //      needs are read from their lanes' registers (no LDS traffic)
+        auto point = [&](const int k, float &x, float &y, float &a) {   // k wave-uniform
+          const int l = k & (kBatch - 1);
+          const bool crest = k < kBatch;
+          x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crest ? cx : tx), l));
+          y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crest ? cy : ty), l));
+          const float av = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(A), l));
+          a = crest ? av : -av;
+        };
+        auto quadrant = [&](f32x16 &cq, const int xq, const int yq, const uint32_t bit) {
+          if (xq >= T.tw || yq >= T.th) return;   // quadrant outside a narrow tile
+          uint64_t m0 = __ballot(live && reaches(cx, cy, rc, xq, yq));
+          uint64_t m1 = __ballot(live && reaches(tx, ty, rc, xq, yq));
+          if (!(m0 | m1)) return;   // wave-uniform
+          touched |= bit;
+          if constexpr (kRadial) {
+            // no outer-product form: each lane accumulates its 16 cells of the
+            // quadrant (the matrix-core output layout) point by point
+            const float dxl = (float)(xq + (lane & 31)), ybase = (float)(yq + 4 * (lane >> 5));
+            for (int kk = pop_point(m0, m1); kk >= 0; kk = pop_point(m0, m1)) {
+              float px, py, pa;
+              point(kk, px, py, pa);
+              const float dx = dxl - px, dx2 = dx * dx;
+#pragma unroll
+              for (int r = 0; r < 16; ++r) {
+                const float dy = ybase + (float)(8 * (r >> 2) + (r & 3)) - py;
+                cq[r] += pa * wrev(__builtin_amdgcn_sqrtf(dx2 + dy * dy) * qs);
+              }
+            }
+          } else {
+            // rank-2 update D += W_y(:, k1 k2) [A_k1 W_x(k1, :); A_k2 W_x(k2, :)]
+            // per pair of points (lanes 0-31 supply the first, 32-63 the
+            // second, which is a zero-amplitude copy of the first when the
+            // count is odd)
+            const float yrow = (float)(yq + (lane & 31)), xcol = (float)(xq + (lane & 31));
+            const bool lo = lane < 32;
+            for (int j1 = pop_point(m0, m1); j1 >= 0; j1 = pop_point(m0, m1)) {   // wave-uniform
+              const int j2 = pop_point(m0, m1);
+              float x1, y1, a1, x2, y2, a2;
+              point(j1, x1, y1, a1);
+              if (j2 >= 0) point(j2, x2, y2, a2);
+              else { x2 = x1; y2 = y1; a2 = 0.f; }
+              const float px = lo ? x1 : x2, py = lo ? y1 : y2, pa = lo ? a1 : a2;
+              const float a = wrev((yrow - py) * qs);
+              const float bw = pa * wrev((xcol - px) * qs);
+              cq = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bw, cq, 0, 0, 0);
+            }
+          }
+        };
+        quadrant(cq0, 0, 0, 1u);
+        quadrant(cq1, 32, 0, 2u);
+        quadrant(cq2, 0, 32, 4u);
+        quadrant(cq3, 32, 32, 8u);
+      }
+      mark(PROF_BUCKET + b);
+      k0 = k1; b0 = b1; c0 = c1;
+      k1 = k2; b1 = b2; c1 = c2;
+      r1 = r2;
+      in0 = in1;
     }
     __syncthreads();
+    mark(PROF_WAIT);
+    // the quadrant accumulators into the tile: in round i wavefront w adds
+    // its accumulator of quadrant (w + i) mod 4, so the four wavefronts of a
+    // round touch disjoint cells and plain read-modify-writes suffice
+    if (__syncthreads_or(touched != 0u)) {   // block-uniform
+      auto add_quadrant = [&](const f32x16 &cq, const int xq, const int yq) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = yq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          acc[row][xq + (lane & 31)] += cq[r];
+        }
+      };
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = (wave + i) & 3;   // wave-uniform
+        if ((touched >> q) & 1u) {
+          if (q == 0) add_quadrant(cq0, 0, 0);
+          else if (q == 1) add_quadrant(cq1, 32, 0);
+          else if (q == 2) add_quadrant(cq2, 0, 32);
+          else add_quadrant(cq3, 32, 32);
+        }
+        __syncthreads();
+      }
+    }
     // time spent on this item's particles, for the next frame's plan
     if (tid == 0 && !direct)
       atomicAdd(&d.tile_meas[tile], (uint32_t)min<uint64_t>(__builtin_amdgcn_s_memrealtime() - t_work, 0x3FFFFFFFull));
@@ -685,6 +813,12 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat(Dev d, int t0, int nt, co
       for (int c = tid; c < kTile * kTile; c += kThreads) dst[c] = acc[c / kTile][c % kTile];
     }
     __syncthreads();
+    mark(PROF_EPILOGUE);
+  }
+  if constexpr (kProf) {
+    __syncthreads();
+    for (int i = tid; i < PROF_N; i += kThreads)
+      if (s_prof[i]) atomicAdd(&d.splat_prof[i], s_prof[i]);
   }
 }
 
@@ -761,21 +895,27 @@ void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipS
 }
 
 // The splat kernel for the record form and kernel shape of d.
-template <bool kRadial>
+template <bool kRadial, bool kProf>
 void splat_launch(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,
                   int64_t out_off, hipStream_t st) {
   if (d.compact)
-    hipLaunchKernelGGL((k_splat<RecCompact, kRadial>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+    hipLaunchKernelGGL((k_splat<RecCompact, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
                        (const RecCompact *)recs, n, raw, blend, out_off);
   else
-    hipLaunchKernelGGL((k_splat<RecWide, kRadial>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+    hipLaunchKernelGGL((k_splat<RecWide, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
                        (const RecWide *)recs, n, raw, blend, out_off);
 }
 
 void splat_launch_any(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,
                       int64_t out_off, hipStream_t st) {
-  if (d.radial) splat_launch<true>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
-  else splat_launch<false>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+  const bool prof = d.splat_profile && d.splat_prof && !recs;
+  if (d.radial) {
+    if (prof) splat_launch<true, true>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+    else splat_launch<true, false>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+  } else {
+    if (prof) splat_launch<false, true>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+    else splat_launch<false, false>(d, grid, t0, ntiles, recs, n, raw, blend, out_off, st);
+  }
 }
 
 void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st) {

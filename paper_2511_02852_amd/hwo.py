@@ -21,7 +21,7 @@ STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "spla
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
-           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes", "hwo_sample_probes_static",
+           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes", "hwo_sample_probes_static", "hwo_set_splat_profile", "hwo_read_splat_profile",
            "hwo_snapshot_size", "hwo_snapshot", "hwo_restore"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
@@ -100,6 +100,8 @@ def lib():
         "hwo_record_bytes": (i32, [vp]),
         "hwo_sample_probes": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float), i32]),
         "hwo_sample_probes_static": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float)]),
+        "hwo_set_splat_profile": (C.c_int, [vp, i32]),
+        "hwo_read_splat_profile": (C.c_int, [vp, P(C.c_double), i32]),
         "hwo_snapshot_size": (C.c_int, [vp, P(i64)]),
         "hwo_snapshot": (C.c_int, [vp, vp, i64]),
         "hwo_restore": (C.c_int, [vp, vp, i64]),
@@ -318,6 +320,19 @@ class Ocean:
         n = np.zeros(len(STAGES), dtype=np.int64)
         self._check(self.L.hwo_stage_times(self.h, _p(ms, C.c_double), _p(n, C.c_int64), len(STAGES)))
         return {s: (float(ms[i]), int(n[i])) for i, s in enumerate(STAGES)}
+
+    def set_splat_profile(self, on: bool):
+        """Start (clearing the accumulators) or stop the splat's per-bucket profile."""
+        self._check(self.L.hwo_set_splat_profile(self.h, 1 if on else 0))
+
+    def splat_profile(self):
+        """Accumulated splat profile: wavefront ticks per category (set-up,
+        decode, wait, epilogue and one per bucket) and points visited per bucket."""
+        v = np.zeros(36)
+        self._check(self.L.hwo_read_splat_profile(self.h, _p(v, C.c_double), 36))
+        nb = self.scene.spectrum.n_buckets
+        return {"setup": v[0], "decode": v[1], "wait": v[2], "epilogue": v[3],
+                "bucket": v[4:4 + nb].copy(), "points": v[20:20 + nb].copy()}
 
     def time_stage(self, stage: str, reps: int = 20) -> float:
         """Mean ms per back-to-back launch of a repeatable stage on the finished frame."""

@@ -646,3 +646,35 @@ def test_static_source_outside_patch_emits_dead_particles():
     o.step(10)
     check_integer_state(g, o, s)
     assert o.counts(0)[:, 4].sum() > 0
+
+
+def test_splat_profile_accounts_every_bucket():
+    """The splat's per-bucket profile: every live particle's crest and
+    trough are visited by at least one tile (points >= 2 x live per bucket),
+    buckets with particles take time, and profiling changes no integer
+    state (the oracle's after the same steps)."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.c2()
+    g, o = make(s, compact=True, batched=True)
+    g.step(100)
+    live0 = g.counts(0)[:, 0]
+    g.set_splat_profile(True)
+    g.step(20)
+    g.sync()
+    prof = g.splat_profile()
+    g.set_splat_profile(False)
+    o.step(120)
+    check_integer_state(g, o, s)
+    live = g.counts(0)[:, 0]
+    say(f"profile points={prof['points'].tolist()} live={live.tolist()}")
+    # each of the 20 frames visits every live particle at least once (live
+    # counts move by a few percent over 20 frames)
+    assert np.all(prof["points"] >= 2 * 20 * np.minimum(live0, live) * 0.95)
+    assert np.all(prof["bucket"][live > 0] > 0)
+    assert prof["decode"] > 0 and prof["setup"] > 0 and prof["epilogue"] > 0
+    # off: nothing more accumulates
+    before = g.splat_profile()
+    g.step(3)
+    g.sync()
+    after = g.splat_profile()
+    assert np.array_equal(before["points"], after["points"])
