@@ -142,6 +142,7 @@ struct Dev {
   const SourceDev *sources;
   const int32_t *src_order;    // sources sorted by patch
   const int2 *V;               // [nb][kNCode] velocity per step
+  const int2 *Vbin;            // [nb][kDirBins] velocity of each direction bin's code (boundary particles)
   const float2 *UC;            // [kNCode] unit direction
   const float *afac;           // [nb][kNCode] stratified-direction amplitude factor sqrt(2 pi Dir); null: inverse-CDF mode
   const uint32_t *cdf;         // [nb][side pair][64] inclusive integer CDF
@@ -287,6 +288,18 @@ __device__ inline float particle_amp(const Dev &d, const Part &p) {
   const uint32_t lv = m_level(m);
   const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;
   return s.B * d.ring_m[s.ring0 + m_slot(m)] * inv3;
+}
+
+// Velocity per step of a particle.  Boundary particles drawn from the 64
+// direction bins (inverse-CDF mode, d.afac null) carry a bin's code, so their
+// velocities come from the small per-bin table, which stays in the L1 cache;
+// other codes (ring particles, stratified directions) read the full table.
+__device__ __forceinline__ int2 velocity(const Dev &d, int bucket, int code, bool boundary) {
+  if (boundary && !d.afac) {
+    const int t = ((code - d.wind_code - kNCode / 2 - kNCode / (2 * kDirBins)) % kNCode + kNCode) % kNCode;
+    if (t % (kNCode / kDirBins) == 0) return d.Vbin[bucket * kDirBins + t / (kNCode / kDirBins)];
+  }
+  return d.V[bucket * kNCode + code];   // any other code (caller-placed records included)
 }
 
 // ---------------------------------------------------------------- output tiles

@@ -84,7 +84,7 @@ __device__ __forceinline__ void deposit_rec(const Dev &d, const Rec &r, int64_t 
                                             const StepPatch &Wp, float *D, int pitch, int tx0, int ty0, int dw,
                                             int dh, int R, float inv_dxu) {
   const Part q = RecIO<Rec>::unpack(r, n);
-  const int2 v = d.V[b * kNCode + q.code];
+  const int2 v = velocity(d, b, q.code, m_kind(q.meta) == 0);
   const int64_t px = (int64_t)q.ox + (((int64_t)q.age * v.x) >> 12);
   const int64_t py = (int64_t)q.oy + (((int64_t)q.age * v.y) >> 12);
   const int64_t x = px - (int64_t)Wp.wx * P.dxu, y = py - (int64_t)Wp.wy * P.dxu;
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
         for (int j = 0; j < kBatch; ++j) {
           if (e0 + j * kThreads + (int)threadIdx.x < c_hi) {
             q[j] = RecIO<Rec>::unpack(rr[j], n);
-            v[j] = d.V[b * kNCode + q[j].code];
+            v[j] = velocity(d, b, q[j].code, m_kind(q[j].meta) == 0);
             to[j] = d.toff[b * kNCode + q[j].code];
             A[j] = particle_amp<Rec>(d, q[j]);
           }

@@ -184,10 +184,10 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
 // ---------------------------------------------------------------- update
 // Survival and bin key of a particle at age `age` (>= 0).  -1 if it dies.
 __device__ __forceinline__ int32_t survive_key(const Dev &d, const PatchDev &P, const StepPatch &W,
-                                               int bucket, int code, int32_t ox, int32_t oy, int32_t age,
-                                               int64_t &px, int64_t &py) {
+                                               int bucket, int code, bool boundary, int32_t ox, int32_t oy,
+                                               int32_t age, int64_t &px, int64_t &py) {
   if (age > kAgeMax) return -1;
-  const int2 v = d.V[bucket * kNCode + code];
+  const int2 v = velocity(d, bucket, code, boundary);
   px = (int64_t)ox + (((int64_t)age * v.x) >> 12);
   py = (int64_t)oy + (((int64_t)age * v.y) >> 12);
   const int64_t m = d.margin[bucket];
@@ -391,7 +391,8 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       for (int r = 0; r < 3; ++r) {   // constant bound: o[] and key[] stay in registers
         if (r < nout) {
           int64_t px, py;
-          key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, o[r].ox, o[r].oy, o[r].age, px, py);
+          key[r] = survive_key(d, P, W, (int)m_bucket(o[r].meta), o[r].code, m_kind(o[r].meta) == 0, o[r].ox,
+                               o[r].oy, o[r].age, px, py);
           if (key[r] < 0) ++ndead;
         }
       }

@@ -690,6 +690,12 @@ static int finalize(hwo_ocean *o) {
   d.sources = upload(o, o->sdev, &rc);
   d.src_order = upload(o, o->src_order, &rc);
   d.V = upload(o, o->V, &rc);
+  {
+    std::vector<int2> vbin((size_t)nb * kDirBins);
+    for (int i = 0; i < nb; ++i)
+      for (int k = 0; k < kDirBins; ++k) vbin[(size_t)i * kDirBins + k] = o->V[(size_t)i * kNCode + o->codes[k]];
+    d.Vbin = upload(o, vbin, &rc);
+  }
   d.UC = upload(o, o->UC, &rc);
   d.cdf = o->cdf;
   d.cdfQ = o->cdfQ;

@@ -433,7 +433,7 @@ constexpr int kBatch = 64;   // list entries a wavefront takes at a time, one pe
 struct DecIn {
   int32_t ox, oy, age;
   int2 v;          // velocity per step of the code (2^-32 m)
-  float2 u;        // unit direction of the code
+  int32_t code;    // direction code (its unit vector is computed, not loaded)
   float f;         // amplitude (wide form), ring amplitude B m, or the stratified direction factor
   uint32_t flags;  // bit 0 valid, bit 1 ring particle, bits 2-4 level
 };
@@ -443,7 +443,7 @@ __device__ __forceinline__ DecIn dec_load(const Dev &d, const Rec &r, int64_t n,
   DecIn o;
   o.ox = 0; o.oy = 0; o.age = 0;
   o.v = make_int2(0, 0);
-  o.u = make_float2(0.f, 0.f);
+  o.code = 0;
   o.f = 1.f;
   o.flags = 0u;
   if (!valid) return o;
@@ -454,8 +454,8 @@ __device__ __forceinline__ DecIn dec_load(const Dev &d, const Rec &r, int64_t n,
   o.ox = q.ox;
   o.oy = q.oy;
   o.age = q.age;
-  o.v = d.V[b * kNCode + q.code];
-  o.u = d.UC[q.code];
+  o.v = velocity(d, b, q.code, !ring);
+  o.code = q.code;
   if (RecIO<Rec>::kHasAmp) o.f = q.amp;
   else if (ring) o.f = d.ring_amp[m_src(q.meta) * kMaxRing + m_slot(q.meta)];
   else if (d.afac) o.f = d.afac[b * kNCode + q.code];
@@ -694,7 +694,9 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
       const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
       const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
       const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
-      const float tx = cx - rc * in0.u.x, ty = cy - rc * in0.u.y;
+      // unit direction of the code: v_cos / v_sin take revolutions
+      const float rev = (float)in0.code * (1.0f / (float)kNCode);
+      const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
       // the next batch's table loads go out before this batch is splatted
       const DecIn in1 = dec_load<Rec>(d, r1, n, b1, T.p, k1 < nbat && lane < c1);
       if constexpr (kProf)
@@ -762,10 +764,41 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
             }
           }
         };
-        quadrant(cq0, 0, 0, 1u);
-        quadrant(cq1, 32, 0, 2u);
-        quadrant(cq2, 0, 32, 4u);
-        quadrant(cq3, 32, 32, 8u);
+        bool whole = false;
+        if constexpr (!kRadial) whole = 2.f * rc >= 32.f;   // footprints at least a quadrant wide
+        if (whole) {
+          // every pair goes to all quadrants of the tile: the row weights of
+          // the two quadrant rows and the column weights of the two quadrant
+          // columns serve four products (a quadrant a point misses gets zero
+          // weights)
+          uint64_t m0 = __ballot(live && (reaches(cx, cy, rc, 0, 0) || reaches(cx, cy, rc, 32, 32) ||
+                                          reaches(cx, cy, rc, 32, 0) || reaches(cx, cy, rc, 0, 32)));
+          uint64_t m1 = __ballot(live && (reaches(tx, ty, rc, 0, 0) || reaches(tx, ty, rc, 32, 32) ||
+                                          reaches(tx, ty, rc, 32, 0) || reaches(tx, ty, rc, 0, 32)));
+          const bool x1 = T.tw > 32, y1 = T.th > 32;   // right and lower quadrants exist
+          if (m0 | m1) touched |= 1u | (x1 ? 2u : 0u) | (y1 ? 4u : 0u) | (x1 && y1 ? 8u : 0u);
+          const float l32 = (float)(lane & 31);
+          const bool lo = lane < 32;
+          for (int j1 = pop_point(m0, m1); j1 >= 0; j1 = pop_point(m0, m1)) {   // wave-uniform
+            const int j2 = pop_point(m0, m1);
+            float xa, ya, aa, xb, yb, ab;
+            point(j1, xa, ya, aa);
+            if (j2 >= 0) point(j2, xb, yb, ab);
+            else { xb = xa; yb = ya; ab = 0.f; }
+            const float px = lo ? xa : xb, py = lo ? ya : yb, pa = lo ? aa : ab;
+            const float a0 = wrev((l32 - py) * qs), a1 = wrev((l32 + 32.f - py) * qs);
+            const float w0 = pa * wrev((l32 - px) * qs), w1 = pa * wrev((l32 + 32.f - px) * qs);
+            cq0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, w0, cq0, 0, 0, 0);
+            if (x1) cq1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, w1, cq1, 0, 0, 0);
+            if (y1) cq2 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, w0, cq2, 0, 0, 0);
+            if (x1 && y1) cq3 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, w1, cq3, 0, 0, 0);
+          }
+        } else {
+          quadrant(cq0, 0, 0, 1u);
+          quadrant(cq1, 32, 0, 2u);
+          quadrant(cq2, 0, 32, 4u);
+          quadrant(cq3, 32, 32, 8u);
+        }
       }
       mark(PROF_BUCKET + b);
       k0 = k1; b0 = b1; c0 = c1;
