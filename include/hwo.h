@@ -125,6 +125,14 @@ typedef struct {
     int32_t follow;         /* source id that recentres the window, -1 static */
 } hwo_patch;
 
+/* Work partition of the per-bucket splat (the tunable launch parameters of
+ * the batched form; hwo_get_plan / hwo_set_plan / hwo_autotune). */
+typedef struct {
+    int32_t chunk_load;     /* least estimated cost of one splat work item (model units) */
+    int32_t items_target;   /* work items per frame the plan aims for beyond one per output tile */
+    int32_t splat_grid;     /* persistent splat blocks launched; 0: four per compute unit */
+} hwo_plan;
+
 typedef struct {
     double x0, y0;          /* world start (m) */
     double vx, vy;          /* velocity (m/s); zero speed emits nothing */
@@ -318,6 +326,22 @@ int hwo_read_splat_profile(hwo_ocean *o, double *dst, int32_t n);
  * HWO_EINVAL, a call before the first step HWO_ESTATE.  Outputs are rewritten
  * with the same values (up to FP32 summation order). */
 int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep);
+/* Tuning of the per-bucket splat (Sec 4.2: the per-bucket layers of Fig 1's
+ * pairs, here one launch over all tiles of all patches).  hwo_get_plan
+ * reports the current work partition; hwo_set_plan replaces it (chunk_load
+ * 64..2^24, items_target 0..8192, splat_grid 0..65535; HWO_EINVAL
+ * otherwise), effective from the next step (the frame graph is captured
+ * again).  hwo_autotune searches the partition on the current frame: after
+ * at least one step it re-runs the plan, splat and reduce stages (which
+ * rewrite the same heights, up to FP32 summation order) reps times per
+ * candidate, coordinate by coordinate over chunk_load, items_target and
+ * splat_grid, keeps the fastest, sets it and reports it with its time and
+ * that of the partition it started from (milliseconds per plan + splat +
+ * reduce).  Integer state is never touched.  HWO_ESTATE before the first
+ * step, HWO_EINVAL with texel layers (synth 1) or reps < 1.  Synchronise. */
+int hwo_get_plan(hwo_ocean *o, hwo_plan *out);
+int hwo_set_plan(hwo_ocean *o, const hwo_plan *plan);
+int hwo_autotune(hwo_ocean *o, int32_t reps, hwo_plan *best, double *best_ms, double *start_ms);
 /* Bytes of particle storage per record for the active form (16 or 32): the
  * particle attributes of Sec 3.2 (position, direction, bucket, amplitude
  * source, birth); -1 for NULL. */

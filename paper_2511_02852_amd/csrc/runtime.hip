@@ -103,6 +103,7 @@ struct hwo_ocean {
   uint32_t *cdf = nullptr, *cdfQ = nullptr;
   int update_grid = 1024;
   int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
+  int splat_grid = 0;              // persistent splat blocks launched (0: four times target_blocks)
   int items_target = 4096;          // splat work items per frame the plan aims for (beyond one per tile; set per scene)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -888,7 +889,9 @@ static void launch_stage(hwo_ocean *o, int stage, const PatchArg *g) {
     case ST_SCATTER: launch_update(d, g->p0, g->p1, true, o->update_grid, o->st); break;
     case ST_PLAN: launch_splat_plan(d, g->t0, g->t1 - g->t0, o->items_target, o->st); break;
     case ST_SPLAT:
-      launch_splat_tiles(d, g->t0, g->t1 - g->t0, std::max(1, std::min(4 * o->target_blocks, d.max_items)), o->st);
+      launch_splat_tiles(d, g->t0, g->t1 - g->t0,
+                         std::max(1, std::min(o->splat_grid > 0 ? o->splat_grid : 4 * o->target_blocks, d.max_items)),
+                         o->st);
       break;
     case ST_REDUCE: launch_splat_reduce(d, g->t0, g->t1 - g->t0, o->st); break;
     case ST_BINPLAN: launch_bin_plan(d, d.nbins, d.ntiles, o->items_target, o->st); break;
@@ -1542,6 +1545,126 @@ int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep
   (void)hipEventDestroy(b);
   HWO_CHECK(hipGetLastError());
   *ms_per_rep = (double)ms / reps;
+  return HWO_OK;
+}
+
+static void drop_graph(hwo_ocean *o) {
+  if (o->exec) (void)hipGraphExecDestroy(o->exec);
+  if (o->graph) (void)hipGraphDestroy(o->graph);
+  o->exec = nullptr;
+  o->graph = nullptr;
+}
+
+int hwo_get_plan(hwo_ocean *o, hwo_plan *out) {
+  if (!o || !out) return HWO_EINVAL;
+  int rc = finalize(o);
+  if (rc) return rc;
+  out->chunk_load = (int32_t)o->dev.chunk_load;
+  out->items_target = o->items_target;
+  out->splat_grid = o->splat_grid;
+  return HWO_OK;
+}
+
+int hwo_set_plan(hwo_ocean *o, const hwo_plan *p) {
+  if (!o || !p) return HWO_EINVAL;
+  if (p->chunk_load < 64 || p->chunk_load > (1 << 24) || p->items_target < 0 || p->items_target > 8192 ||
+      p->splat_grid < 0 || p->splat_grid > 65535)
+    return o->fail(HWO_EINVAL, "plan parameter out of range");
+  int rc = finalize(o);
+  if (rc) return rc;
+  HWO_CHECK(hipStreamSynchronize(o->st));
+  o->dev.chunk_load = (uint32_t)p->chunk_load;
+  o->items_target = p->items_target;
+  o->splat_grid = p->splat_grid;
+  drop_graph(o);   // the plan parameters are kernel arguments of the captured frame
+  return HWO_OK;
+}
+
+// Milliseconds per (plan, splat, reduce) on the current frame, after two
+// untimed rounds that let the partition feedback settle.
+static int time_partition(hwo_ocean *o, int reps, double *ms) {
+  const std::vector<PatchArg> groups = launch_groups(o);
+  auto round = [&]() {
+    for (const auto &gp : groups) {
+      launch_stage(o, ST_PLAN, &gp);
+      launch_stage(o, ST_SPLAT, &gp);
+      launch_stage(o, ST_REDUCE, &gp);
+    }
+  };
+  round();
+  round();
+  hipEvent_t a = nullptr, b = nullptr;
+  HWO_CHECK(hipEventCreate(&a));
+  HWO_CHECK(hipEventCreate(&b));
+  HWO_CHECK(hipEventRecord(a, o->st));
+  for (int k = 0; k < reps; ++k) round();
+  HWO_CHECK(hipEventRecord(b, o->st));
+  HWO_CHECK(hipEventSynchronize(b));
+  float t = 0.f;
+  HWO_CHECK(hipEventElapsedTime(&t, a, b));
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  HWO_CHECK(hipGetLastError());
+  *ms = (double)t / reps;
+  return HWO_OK;
+}
+
+int hwo_autotune(hwo_ocean *o, int32_t reps, hwo_plan *best, double *best_ms, double *start_ms) {
+  if (!o || !best || !best_ms || !start_ms || reps < 1) return HWO_EINVAL;
+  if (o->cfg.synth == 1) return o->fail(HWO_EINVAL, "the texel-layer synthesis has no splat partition");
+  if (o->n_host < 1) return o->fail(HWO_ESTATE, "autotune needs a completed step");
+  int rc = collect_timing(o);
+  if (rc) return rc;
+  Dev &d = o->dev;
+  hwo_plan cur{(int32_t)d.chunk_load, o->items_target, o->splat_grid};
+  auto apply = [&](const hwo_plan &p) {
+    d.chunk_load = (uint32_t)p.chunk_load;
+    o->items_target = p.items_target;
+    o->splat_grid = p.splat_grid;
+  };
+  double t_cur = 0.0;
+  rc = time_partition(o, reps, &t_cur);
+  if (rc) return rc;
+  *start_ms = t_cur;
+  const int room = std::min(8192, d.max_items - d.ntiles);
+  const int tb = o->target_blocks;   // four per compute unit
+  const std::vector<int32_t> chunks = {1000, 1750, 2500, 3500, 5000, 7000, 10000, 14000};
+  const std::vector<int32_t> items = {256, 512, 1024, 2048, 4096, 8192};
+  const std::vector<int32_t> grids = {tb / 2, tb, 2 * tb, 4 * tb, 8 * tb};
+  // two sweeps of coordinate descent
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    for (int coord = 0; coord < 3; ++coord) {
+      const std::vector<int32_t> &vals = coord == 0 ? chunks : coord == 1 ? items : grids;
+      for (int32_t v : vals) {
+        hwo_plan p = cur;
+        if (coord == 0) p.chunk_load = v;
+        if (coord == 1) {
+          if (v > room) continue;
+          p.items_target = v;
+        }
+        if (coord == 2) p.splat_grid = std::max(1, v);
+        if (p.chunk_load == cur.chunk_load && p.items_target == cur.items_target && p.splat_grid == cur.splat_grid)
+          continue;
+        apply(p);
+        double t = 0.0;
+        rc = time_partition(o, reps, &t);
+        if (rc) return rc;
+        if (t < t_cur) {
+          t_cur = t;
+          cur = p;
+        }
+      }
+      apply(cur);
+    }
+  }
+  apply(cur);
+  drop_graph(o);
+  // leave the frame's outputs from the chosen partition
+  double t = 0.0;
+  rc = time_partition(o, 1, &t);
+  if (rc) return rc;
+  *best = cur;
+  *best_ms = t_cur;
   return HWO_OK;
 }
 

@@ -21,8 +21,9 @@ STAGES = ["params", "fft_a", "fft_b", "count", "scan", "scatter", "splat", "spla
 EXPORTS = ["hwo_create_ocean", "hwo_destroy_ocean", "hwo_last_error", "hwo_set_spectrum", "hwo_add_patch",
            "hwo_add_source", "hwo_set_bins", "hwo_step", "hwo_sync", "hwo_step_index", "hwo_read_heightmaps",
            "hwo_read_counts", "hwo_read_buckets", "hwo_tile_dims", "hwo_read_tiles", "hwo_read_particles", "hwo_test_splat",
-           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes", "hwo_sample_probes_static", "hwo_set_splat_profile", "hwo_read_splat_profile",
-           "hwo_snapshot_size", "hwo_snapshot", "hwo_restore"]
+           "hwo_set_timing", "hwo_stage_times", "hwo_time_stage", "hwo_record_bytes", "hwo_sample_probes",
+           "hwo_sample_probes_static", "hwo_set_splat_profile", "hwo_read_splat_profile", "hwo_get_plan",
+           "hwo_set_plan", "hwo_autotune", "hwo_snapshot_size", "hwo_snapshot", "hwo_restore"]
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -48,6 +49,10 @@ class HwoSpectrum(C.Structure):
 class HwoPatch(C.Structure):
     _fields_ = [("anchor_x", C.c_double), ("anchor_y", C.c_double), ("nx", C.c_int32), ("ny", C.c_int32),
                 ("dx", C.c_double), ("eta", C.c_double), ("blend_band", C.c_double), ("follow", C.c_int32)]
+
+
+class HwoPlan(C.Structure):
+    _fields_ = [("chunk_load", C.c_int32), ("items_target", C.c_int32), ("splat_grid", C.c_int32)]
 
 
 class HwoSource(C.Structure):
@@ -98,6 +103,9 @@ def lib():
         "hwo_stage_times": (C.c_int, [vp, P(C.c_double), P(i64), i32]),
         "hwo_time_stage": (C.c_int, [vp, i32, i32, P(C.c_double)]),
         "hwo_record_bytes": (i32, [vp]),
+        "hwo_get_plan": (C.c_int, [vp, P(HwoPlan)]),
+        "hwo_set_plan": (C.c_int, [vp, P(HwoPlan)]),
+        "hwo_autotune": (C.c_int, [vp, i32, P(HwoPlan), P(C.c_double), P(C.c_double)]),
         "hwo_sample_probes": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float), i32]),
         "hwo_sample_probes_static": (C.c_int, [vp, P(C.c_double), i64, P(C.c_float)]),
         "hwo_set_splat_profile": (C.c_int, [vp, i32]),
@@ -333,6 +341,25 @@ class Ocean:
         nb = self.scene.spectrum.n_buckets
         return {"setup": v[0], "decode": v[1], "wait": v[2], "epilogue": v[3],
                 "bucket": v[4:4 + nb].copy(), "points": v[20:20 + nb].copy()}
+
+    def get_plan(self) -> dict:
+        """Current work partition of the splat (chunk_load, items_target, splat_grid)."""
+        p = HwoPlan()
+        self._check(self.L.hwo_get_plan(self.h, C.byref(p)))
+        return {"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid}
+
+    def set_plan(self, chunk_load: int, items_target: int, splat_grid: int = 0):
+        p = HwoPlan(int(chunk_load), int(items_target), int(splat_grid))
+        self._check(self.L.hwo_set_plan(self.h, C.byref(p)))
+
+    def autotune(self, reps: int = 5):
+        """Search the splat partition on the current frame; returns (plan,
+        ms per plan + splat + reduce of the chosen plan, of the starting one)."""
+        p = HwoPlan()
+        best, start = C.c_double(), C.c_double()
+        self._check(self.L.hwo_autotune(self.h, int(reps), C.byref(p), C.byref(best), C.byref(start)))
+        return ({"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid},
+                float(best.value), float(start.value))
 
     def time_stage(self, stage: str, reps: int = 20) -> float:
         """Mean ms per back-to-back launch of a repeatable stage on the finished frame."""

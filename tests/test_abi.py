@@ -139,6 +139,12 @@ def test_call_order_errors(L):
     assert L.hwo_sample_probes_static(h, None, 2, out) == hwo.HWO_EINVAL
     assert L.hwo_sample_probes_static(h, xy, 131073, out) == hwo.HWO_ERANGE   # beyond the static scratch
     assert L.hwo_sample_probes_static(h, xy, 2, out) == hwo.HWO_ESTATE        # nothing built, no step
+    for bad in ((10, 100, 0), (3500, -1, 0), (3500, 9000, 0), (3500, 100, -2), (1 << 25, 0, 0)):
+        assert L.hwo_set_plan(h, C.byref(hwo.HwoPlan(*bad))) == hwo.HWO_EINVAL, bad
+    assert L.hwo_set_plan(h, None) == hwo.HWO_EINVAL
+    plan, t1, t2 = hwo.HwoPlan(), C.c_double(), C.c_double()
+    assert L.hwo_autotune(h, 0, C.byref(plan), C.byref(t1), C.byref(t2)) == hwo.HWO_EINVAL
+    assert L.hwo_autotune(h, 3, C.byref(plan), C.byref(t1), C.byref(t2)) == hwo.HWO_ESTATE   # no step yet
     nbytes = C.c_int64()
     assert L.hwo_snapshot_size(h, C.byref(nbytes)) == hwo.HWO_ESTATE   # nothing to save yet
     img = (C.c_char * 16)()
