@@ -55,7 +55,7 @@ def lib():
         "orc_error": (C.c_char_p, [vp]),
         "orc_set_spectrum": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, i32, dbl, dbl, dbl, i32, dbl, i32, i32, i32, i32]),
         "orc_add_patch": (C.c_int, [vp, dbl, dbl, i32, i32, dbl, dbl, dbl, i32]),
-        "orc_add_source": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32]),
+        "orc_add_source": (C.c_int, [vp, dbl, dbl, dbl, dbl, dbl, dbl, i32, i32, dbl, dbl]),
         "orc_set_bins": (C.c_int, [vp, P(i32)]),
         "orc_set_synthesis": (C.c_int, [vp, i32, i32]),
         "orc_normals": (C.c_int, [vp, i32, P(dbl), P(dbl)]),
@@ -168,7 +168,8 @@ class Oracle:
                                              p.blend_band, p.follow))
         for s in scene.sources:
             self._check(self.L.orc_add_source(h, s.x0, s.y0, s.vx, s.vy, s.radius, s.draft,
-                                              s.ring_n, s.patch))
+                                              s.ring_n, s.patch, float(getattr(s, "heave_amp", 0.0)),
+                                              float(getattr(s, "heave_period", 0.0))))
         self._check(self.L.orc_set_synthesis(h, int(getattr(scene, "synth", 0)), int(getattr(scene, "kernel", 0))))
         b = bins if bins is not None else scene.bins
         if b is not None:
@@ -309,10 +310,10 @@ class Oracle:
         return int(v[0]), int(v[1])
 
     def source_info(self, s: int):
-        out = np.zeros(10)
+        out = np.zeros(12)
         self._check(self.L.orc_source_info(self.h, s, _p(out, C.c_double)))
         return dict(bucket=int(out[0]), E=int(out[1]), B=out[2], heading=out[3], sum_abs=out[4],
-                    T=[int(x) for x in out[5:9]], a0=int(out[9]))
+                    T=[int(x) for x in out[5:9]], a0=int(out[9]), Eh=int(out[10]), Bh=out[11])
 
     def inject_count(self, p, i, pair, n) -> int:
         return int(self.L.orc_inject_count(self.h, p, i, pair, n))

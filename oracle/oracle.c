@@ -80,6 +80,10 @@ typedef struct {
     double x0, y0, vx, vy, R, draft, speed, heading, B, sum_abs;
     int32_t ne, patch, bucket, a0;
     int64_t E, T[LMAX_CAP];
+    /* vertical (heave) motion z(t) = heave_a sin(2 pi t / heave_T); rings
+     * every Eh steps carry the volume the disc displaced since the last one */
+    double heave_a, heave_T, Bh;
+    int64_t Eh;
     double *m;
     int64_t *Ox, *Oy;
 } src_t;
@@ -462,11 +466,12 @@ int orc_patch_bucket(const orc_ocean *o, int32_t p, int32_t i, double *out) {
  * radius; the crest volume of one emission equals the volume swept by the
  * disc since the previous emission (ring model of the design notes). */
 int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,
-                   double draft, int32_t ring_n, int32_t patch) {
+                   double draft, int32_t ring_n, int32_t patch, double heave_a, double heave_T) {
     if (!o->have_spec) return fail(o, "set_spectrum first");
     if (o->stepped) return fail(o, "scene is fixed after the first step");
     if (patch < 0 || patch >= o->np) return fail(o, "source patch out of range");
     if (!(radius > 0) || !(draft >= 0)) return fail(o, "bad source radius/draft");
+    if (!(heave_a >= 0) || (heave_a > 0 && !(heave_T > 0))) return fail(o, "bad heave amplitude/period");
     if (ring_n < 1 || ring_n > 128 || (NCODE / 81) % ring_n != 0) return fail(o, "ring_n must divide 128");
     o->sr = (src_t *)realloc(o->sr, sizeof(src_t) * (size_t)(o->ns + 1));
     src_t *s = &o->sr[o->ns];
@@ -512,8 +517,27 @@ int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, dou
         int64_t T = (int64_t)floor(x) + 1;
         s->T[L] = T < 0 ? 0 : T;
     }
+    /* Vertical motion (Sec 4.3: vertical motions trigger ring ripples).  A
+     * ring leaves every Eh steps, the time the previous one needs to travel
+     * half a radius at the bucket's speed; its n_e crests share the volume
+     * pi R^2 dz the disc pushed out since the previous ring (dz = drop of
+     * the disc; a rising disc gives troughs first), each crest of volume
+     * A r_b^2 with the separable raised cosine: A = pi R^2 dz / (n_e r_b^2). */
+    s->heave_a = heave_a;
+    s->heave_T = heave_T;
+    if (heave_a > 0) {
+        double e = floor(0.5 * rb / (cb * o->dt));
+        s->Eh = e < 1.0 ? 1 : (int64_t)e;
+        s->Bh = M_PI * radius * radius * heave_a / ((double)ring_n * rb * rb);
+    }
     o->ns += 1;
     return 0;
+}
+
+/* Disc elevation of source s at step n over its heave amplitude:
+ * sin(2 pi n dt / heave_T). */
+static double heave_z(const orc_ocean *o, const src_t *s, int64_t n) {
+    return sin(2.0 * M_PI * ((double)n * o->dt) / s->heave_T);
 }
 
 int orc_source_info(const orc_ocean *o, int32_t si, double *out) {
@@ -526,6 +550,8 @@ int orc_source_info(const orc_ocean *o, int32_t si, double *out) {
     out[4] = s->sum_abs;
     for (int L = 0; L < LMAX_CAP; ++L) out[5 + L] = (double)s->T[L];
     out[9] = s->a0;
+    out[10] = (double)s->Eh;
+    out[11] = s->Bh;
     return 0;
 }
 
@@ -644,7 +670,7 @@ static int step_once(orc_ocean *o) {
         int64_t age = n - q->birth;
         int nout = 1;
         out[0] = *q;
-        if (q->kind == 1 && q->level < o->lmax && age >= o->sr[q->src].T[q->level]) {
+        if (q->kind >= 1 && q->level < o->lmax && age >= o->sr[q->src].T[q->level]) {
             int32_t off = (int32_t)(o->sr[q->src].a0 / ipow3(q->level + 1));
             out[0].level = q->level + 1;
             out[1] = out[0];
@@ -718,33 +744,39 @@ static int step_once(orc_ocean *o) {
         }
     }
 
-    /* source ring emission */
+    /* source ring emission: the horizontal-motion ring (kind 1) and the
+     * vertical-motion ring (kind 2), each on its own cadence */
     for (int si = 0; si < o->ns; ++si) {
         const src_t *s = &o->sr[si];
-        if (s->E <= 0 || ((n - 1) % s->E) != 0) continue;
+        const int horizontal = s->E > 0 && ((n - 1) % s->E) == 0;
+        const int vertical = s->heave_a > 0 && ((n - 1) % s->Eh) == 0;
+        if (!horizontal && !vertical) continue;
         patch_t *pt = &o->pt[s->patch];
         double xs, ys;
         source_pos(o, s, n, &xs, &ys);
         int64_t sx = llround((xs - pt->ax) * UNIT);
         int64_t sy = llround((ys - pt->ay) * UNIT);
-        for (int j = 0; j < s->ne; ++j) {
-            prt_t q;
-            memset(&q, 0, sizeof q);
-            q.ox = sx + s->Ox[j];
-            q.oy = sy + s->Oy[j];
-            q.birth = n;
-            q.code = j * s->a0;
-            q.level = 0;
-            q.kind = 1;
-            q.bucket = s->bucket;
-            q.patch = s->patch;
-            q.src = si;
-            q.slot = j;
-            pt->cnt[s->bucket][C_EMIT] += 1;
-            if (alive(o, &q, n))
-                push(o, &NP, &nn, &cap, &q);
-            else
-                pt->cnt[s->bucket][C_DIED] += 1;
+        for (int kind = 1; kind <= 2; ++kind) {
+            if (kind == 1 ? !horizontal : !vertical) continue;
+            for (int j = 0; j < s->ne; ++j) {
+                prt_t q;
+                memset(&q, 0, sizeof q);
+                q.ox = sx + s->Ox[j];
+                q.oy = sy + s->Oy[j];
+                q.birth = n;
+                q.code = j * s->a0;
+                q.level = 0;
+                q.kind = kind;
+                q.bucket = s->bucket;
+                q.patch = s->patch;
+                q.src = si;
+                q.slot = j;
+                pt->cnt[s->bucket][C_EMIT] += 1;
+                if (alive(o, &q, n))
+                    push(o, &NP, &nn, &cap, &q);
+                else
+                    pt->cnt[s->bucket][C_DIED] += 1;
+            }
         }
     }
 
@@ -1019,6 +1051,8 @@ static double amplitude(const orc_ocean *o, const prt_t *q) {
         return pt->A[q->bucket] * sqrt(2.0 * M_PI * dir_s(orc_spread(o, o->w[q->bucket]), th));
     }
     const src_t *s = &o->sr[q->src];
+    if (q->kind == 2)   /* heave ring: the volume displaced between its birth and the previous ring */
+        return s->Bh * (heave_z(o, s, q->birth - s->Eh) - heave_z(o, s, q->birth)) / (double)ipow3(q->level);
     return s->B * s->m[q->slot] / (double)ipow3(q->level);
 }
 
@@ -1414,7 +1448,8 @@ int orc_load(orc_ocean *o, int64_t n, const int64_t *recs, int64_t count) {
         q->src = (int32_t)d[8];
         q->slot = (int32_t)d[9];
         if (q->patch < 0 || q->patch >= o->np || q->bucket < 0 || q->bucket >= o->nb || q->code < 0 ||
-            q->code >= NCODE || q->birth > n || (q->kind == 1 && (q->src < 0 || q->src >= o->ns))) {
+            q->code >= NCODE || q->birth > n || q->kind < 0 || q->kind > 2 ||
+            (q->kind >= 1 && (q->src < 0 || q->src >= o->ns))) {
             free(P);
             return fail(o, "record out of range");
         }
@@ -1453,7 +1488,7 @@ int orc_splat(orc_ocean *o, int32_t p, const int64_t *recs, int64_t n, double *r
         q.src = (int32_t)d[8];
         q.slot = (int32_t)d[9];
         if (q.patch != p || q.bucket < 0 || q.bucket >= o->nb || q.code < 0 || q.code >= NCODE) continue;
-        if (q.kind == 1 && (q.src < 0 || q.src >= o->ns)) continue;
+        if (q.kind < 0 || q.kind > 2 || (q.kind >= 1 && (q.src < 0 || q.src >= o->ns))) continue;
         if (o->synth == 1) keep[nk++] = q;
         else splat_particle(o, pt, raw, &q, wxv, wyv);
     }

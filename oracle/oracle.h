@@ -35,7 +35,7 @@ int orc_set_spectrum(orc_ocean *o, double U10, double fetch, double gamma, doubl
 int orc_add_patch(orc_ocean *o, double ax, double ay, int32_t nx, int32_t ny, double dx,
                   double eta, double band, int32_t follow);
 int orc_add_source(orc_ocean *o, double x0, double y0, double vx, double vy, double radius,
-                   double draft, int32_t ring_n, int32_t patch);
+                   double draft, int32_t ring_n, int32_t patch, double heave_a, double heave_T);
 int orc_set_bins(orc_ocean *o, const int32_t *bin_cells);
 /* Height synthesis: 0 the exact-position splat, 1 texel layers per bucket
  * (bilinear deposit) smoothed by separable x and y passes (Sec 4.2).

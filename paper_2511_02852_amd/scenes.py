@@ -89,7 +89,9 @@ class Source:
 
     (x0, y0): world start position (m); (vx, vy): constant velocity (m/s);
     radius, draft: disc radius and draft (m); ring_n particles per ring;
-    patch: index of the patch that receives the emitted particles.
+    patch: index of the patch that receives the emitted particles;
+    heave_amp, heave_period: vertical motion z(t) = heave_amp sin(2 pi t /
+    heave_period) (m, s); 0 amplitude: no vertical motion.
     """
     x0: float
     y0: float
@@ -99,6 +101,8 @@ class Source:
     draft: float = 1.0
     ring_n: int = 64
     patch: int = 0
+    heave_amp: float = 0.0
+    heave_period: float = 0.0
 
 
 @dataclass

@@ -838,3 +838,113 @@ def test_loaded_state_continues_like_the_original():
     bad[0, 1] = a.nb
     with pytest.raises(oracle.OracleError):
         b.load(b.n, bad)
+
+
+# ---------------------------------------------------------------- vertical motion (Sec 4.3)
+def heave_scene(a=0.1, T=1.5, R=2.0, vx=0.0):
+    """One bucket with r = 1 m = 4 cells (lambda 1-4 m), a 32 m patch and a
+    disc of radius R at its centre heaving as a sin(2 pi t / T)."""
+    sp = scenes.Spectrum(U10=10.0, n_buckets=1, lambda_min=1.0, lambda_max=4.0, eta=1e-6)
+    p = scenes.Patch(anchor_x=0.0, anchor_y=0.0, nx=128, ny=128, dx=0.25)
+    src = scenes.Source(x0=16.0, y0=16.0, vx=vx, vy=0.0, radius=R, draft=1.0, ring_n=64, patch=0,
+                        heave_amp=a, heave_period=T)
+    return scenes.Scene(name="heave", fft_n=64, fft_L=256.0, seed=3, steps=0, spectrum=sp,
+                        patches=[p], sources=[src], bins=[8])
+
+
+def test_heave_ring_volume_equals_displaced_volume():
+    """Every ring a heaving disc emits carries, in its crests, the volume the
+    disc pushed out since the previous ring: sum_j crest volume =
+    pi R^2 (z(t - Eh dt) - z(t)).  Each crest volume is measured from the
+    particle's own splat through its first moment (crest volume times r
+    along its direction, pinned for single pairs), so the identity checks the
+    amplitudes against the disc's motion, not against their formula.  (The
+    moment is exact when the trough sits a whole number of cells from the
+    crest, so each particle is measured with its direction turned to +x,
+    which leaves its amplitude unchanged.)"""
+    s = heave_scene()
+    o = oracle.Oracle(s)
+    si = o.source_info(0)
+    r = o.bucket(0)["r"]
+    c = o.bucket(0)["c"]
+    Eh = si["Eh"]
+    # cadence: a ring leaves each time the previous one has run half a radius
+    assert Eh * c * s.dt <= 0.5 * r < (Eh + 1) * c * s.dt
+    src, p = s.sources[0], s.patches[0]
+    xc = (np.arange(p.nx) + 0.5) * p.dx
+    X, Y = np.meshgrid(xc, xc)
+    z = lambda n: src.heave_amp * math.sin(2 * math.pi * n * s.dt / src.heave_period)
+    checked = 0
+    for k in range(6):
+        n = 1 + k * Eh
+        o.step(n - o.n)
+        P = o.particles()
+        ring = P[(P[:, 2] == 2) & (P[:, 5] == n)]
+        assert ring.shape[0] == src.ring_n
+        vol = 0.0
+        for q in ring:
+            qx = q.copy()
+            qx[4] = 0   # direction +x: the trough r = 4 cells behind the crest along x
+            h = o.splat(0, qx[None, :])
+            vol += (h * X).sum() * p.dx * p.dx / r
+        want = math.pi * src.radius ** 2 * (z(n - Eh) - z(n))
+        assert vol == pytest.approx(want, rel=1e-9, abs=1e-12)
+        checked += 1
+    # only vertical rings from a disc at rest: n_e per emission, ceil(n / Eh) emissions
+    assert int(o.counts(0)[0, 2]) == src.ring_n * (1 + (o.n - 1) // Eh)
+    assert checked == 6
+
+
+def test_heave_ring_is_isotropic():
+    """A vertical-motion ring is the same in every direction: its field is
+    symmetric under the diagonal reflection and both axis reflections about
+    the disc centre (a horizontal-motion ring, signed by the heading, is
+    not)."""
+    s = heave_scene()
+    o = oracle.Oracle(s)
+    Eh = o.source_info(0)["Eh"]
+    o.step(1 + 2 * Eh)
+    P = o.particles()
+    ring = P[(P[:, 2] == 2) & (P[:, 5] == o.n)]
+    h = o.splat(0, ring)
+    scale = np.abs(h).max()
+    assert scale > 0
+    for g in (h.T, h[::-1, :], h[:, ::-1]):
+        assert np.max(np.abs(h - g)) <= 1e-9 * scale
+    # the horizontal-motion ring of a moving disc is antisymmetric along its heading
+    sm = heave_scene(a=0.0, vx=4.0)
+    om = oracle.Oracle(sm)
+    om.step(1)
+    Pm = om.particles()
+    hm = om.splat(0, Pm[Pm[:, 2] == 1])
+    assert np.max(np.abs(hm - hm[:, ::-1])) > 0.1 * np.abs(hm).max()
+
+
+def test_heave_rings_subdivide_and_keep_amplitude():
+    """Vertical-motion ring particles split like horizontal ones (same ages,
+    codes c and c +- a0/3^(L+1)); a complete family's amplitudes sum to the
+    parent's (measured through single-particle splats, as above)."""
+    s = heave_scene()
+    o = oracle.Oracle(s)
+    si = o.source_info(0)
+    T0 = si["T"][0]
+    o.step(T0 + 1)
+    P = o.particles()
+    kids = P[(P[:, 2] == 2) & (P[:, 5] == 1)]
+    assert kids.shape[0] == 3 * 64 and np.all(kids[:, 3] == 1)
+    off = si["a0"] // 3
+    for j in range(64):
+        fam = kids[kids[:, 9] == j]
+        assert sorted(int(x) for x in fam[:, 4]) == sorted([(j * si["a0"] + d) % oracle.NCODE for d in (-off, 0, off)])
+    # amplitudes of a family: three equal thirds of the parent's, via the splat's peak of an isolated copy
+    o2 = oracle.Oracle(s)
+    o2.step(1)
+    parent = o2.particles()
+    parent = parent[(parent[:, 2] == 2) & (parent[:, 9] == 5)][0].copy()
+    o3 = oracle.Oracle(s)
+    o3.seek(o2.n)
+    hp = o3.splat(0, parent[None, :])
+    child = parent.copy()
+    child[3] = 1
+    hc = o3.splat(0, child[None, :])
+    assert np.allclose(hc, hp / 3.0, rtol=0, atol=1e-15 * np.abs(hp).max())
