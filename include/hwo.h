@@ -139,6 +139,8 @@ typedef struct {
     double radius, draft;   /* disc radius and draft (m) */
     int32_t ring_n;         /* particles per ring; must divide 128 */
     int32_t patch;          /* patch receiving the particles */
+    double heave_amp;       /* vertical motion z(t) = heave_amp sin(2 pi t / heave_period) (m); 0: none */
+    double heave_period;    /* (s); > 0 when heave_amp > 0 */
 } hwo_source;
 
 /* Create a handle for one ocean.  The configuration carries the inputs the
@@ -173,9 +175,13 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp);
 int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id);
 /* Add a moving object that disturbs the water (Sec 4.3, object acts on
  * water): a disc emitting rings of particles into patch src->patch, into the
- * bucket whose radius is closest to the disc's.  Max 127; *id receives its
- * index.  HWO_EINVAL for a bad patch index, radius or ring size;
- * HWO_ESTATE after the first step. */
+ * bucket whose radius is closest to the disc's.  Horizontal motion emits a
+ * ring signed by the heading each time the disc has moved half a radius;
+ * vertical motion (heave_amp > 0) emits an isotropic ring each time the
+ * previous one has travelled half a radius, carrying the volume the disc
+ * displaced meanwhile.  Max 127; *id receives its index.  HWO_EINVAL for a
+ * bad patch index, radius, ring size or heave; HWO_ESTATE after the first
+ * step. */
 int hwo_add_source(hwo_ocean *o, const hwo_source *s, int32_t *id);
 /* Per-bucket particle bin edge in cells (n == n_buckets, each 1..4096) of
  * the counting sort that groups particles for the per-bucket splat (Sec 4.2
@@ -232,7 +238,8 @@ int hwo_read_tiles(hwo_ocean *o, int32_t patch, int32_t bucket, int64_t *dst, in
 
 /* Live particles (Sec 3.2 single particle: direction, frequency bucket,
  * amplitude source) as canonical records of 10 int64:
- * patch, bucket, kind (0 boundary, 1 ring), level, code (units of
+ * patch, bucket, kind (0 boundary, 1 ring of horizontal motion, 2 ring of
+ * vertical motion), level, code (units of
  * 2 pi / 10368), birth step, origin x, origin y (2^-20 m from the patch
  * anchor), source (-1 boundary), ring slot.  *n_out receives the count;
  * fails with HWO_ERANGE if max_recs is too small. */

@@ -30,7 +30,8 @@ constexpr uint64_t kStreamInject = 1;
 constexpr uint64_t kStreamH0 = 2;
 
 // ---------------------------------------------------------------- records
-// meta word: level 0-2 | kind 3 | bucket 4-7 | patch 8-14 | src 15-21 | slot 22-28
+// meta word: level 0-2 | kind 3 | bucket 4-7 | patch 8-14 | src 15-21 | slot 22-28 | heave 29
+// (kind 1 is a ring particle; the heave bit marks the rings of vertical motion)
 __host__ __device__ inline uint32_t pack_meta(uint32_t level, uint32_t kind, uint32_t bucket,
                                               uint32_t patch, uint32_t src, uint32_t slot) {
   return level | (kind << 3) | (bucket << 4) | (patch << 8) | (src << 15) | (slot << 22);
@@ -41,6 +42,8 @@ __host__ __device__ inline uint32_t m_bucket(uint32_t m) { return (m >> 4) & 15u
 __host__ __device__ inline uint32_t m_patch(uint32_t m) { return (m >> 8) & 127u; }
 __host__ __device__ inline uint32_t m_src(uint32_t m) { return (m >> 15) & 127u; }
 __host__ __device__ inline uint32_t m_slot(uint32_t m) { return (m >> 22) & 127u; }
+constexpr uint32_t kHeaveBit = 1u << 29;
+__host__ __device__ inline bool m_heave(uint32_t m) { return (m & kHeaveBit) != 0u; }
 
 // Plain form: 32 bytes, every attribute a full 32-bit word, amplitude FP32.
 struct RecWide {
@@ -97,7 +100,24 @@ struct SourceDev {
   float B;
   int32_t patch, bucket, ne, a0, E, ring0;
   int32_t T[kMaxLevel];
+  // vertical motion: a ring every Eh steps (0: none), amplitude
+  // Bh (z(birth - Eh) - z(birth)) with z = sin(2 pi n hf), hf = dt / heave period
+  int32_t Eh;
+  double Bh, hf;
 };
+
+// Amplitude of a vertical-motion ring particle born at step nb, level lv:
+// the volume displaced between the ring before it and its birth.  The phase
+// n dt / heave_T is reduced to [0, 1) in FP64 and its sine taken by the
+// hardware sine, which works in revolutions (absolute error ~1e-7).
+__device__ inline float heave_amp(const SourceDev &S, int64_t nb, uint32_t lv) {
+  double p0 = (double)(nb - S.Eh) * S.hf, p1 = (double)nb * S.hf;
+  p0 -= floor(p0);
+  p1 -= floor(p1);
+  const float dz = __builtin_amdgcn_sinf((float)p0) - __builtin_amdgcn_sinf((float)p1);
+  const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;
+  return (float)S.Bh * dz * inv3;
+}
 
 struct StepPatch {             // per patch, rewritten every step
   int32_t wx, wy;              // window origin (cells)
@@ -278,12 +298,13 @@ template <> struct RecIO<RecCompact> {
 // amplitude (times the direction factor in stratified mode); ring particles
 // B * m_slot / 3^level.
 template <class Rec>
-__device__ inline float particle_amp(const Dev &d, const Part &p) {
+__device__ inline float particle_amp(const Dev &d, const Part &p, int64_t n) {
   if (RecIO<Rec>::kHasAmp) return p.amp;
   uint32_t m = p.meta;
   if (m_kind(m) == 0)
     return d.patches[m_patch(m)].A[m_bucket(m)] * (d.afac ? d.afac[m_bucket(m) * kNCode + p.code] : 1.f);
   const SourceDev &s = d.sources[m_src(m)];
+  if (m_heave(m)) return heave_amp(s, n - p.age, m_level(m));
   // 3^-level, each constant correctly rounded (a select chain, not a local array)
   const uint32_t lv = m_level(m);
   const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;

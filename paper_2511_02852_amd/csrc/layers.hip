@@ -88,7 +88,7 @@ __device__ __forceinline__ void deposit_rec(const Dev &d, const Rec &r, int64_t 
   const int64_t px = (int64_t)q.ox + (((int64_t)q.age * v.x) >> 12);
   const int64_t py = (int64_t)q.oy + (((int64_t)q.age * v.y) >> 12);
   const int64_t x = px - (int64_t)Wp.wx * P.dxu, y = py - (int64_t)Wp.wy * P.dxu;
-  const float A = particle_amp<Rec>(d, q);
+  const float A = particle_amp<Rec>(d, q, n);
   const int2 to = d.toff[b * kNCode + q.code];
   deposit_point(D, pitch, tx0, ty0, dw, dh, R, P.dxu, inv_dxu, x, y, A);
   deposit_point(D, pitch, tx0, ty0, dw, dh, R, P.dxu, inv_dxu, x - to.x, y - to.y, -A);
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kThreads) void k_deposit_x(Dev d, const Rec *__rest
             q[j] = RecIO<Rec>::unpack(rr[j], n);
             v[j] = velocity(d, b, q[j].code, m_kind(q[j].meta) == 0);
             to[j] = d.toff[b * kNCode + q[j].code];
-            A[j] = particle_amp<Rec>(d, q[j]);
+            A[j] = particle_amp<Rec>(d, q[j], n);
           }
         }
 #pragma unroll

@@ -144,8 +144,11 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
   for (int k = tid; k < d.ns; k += kThreads) {
     const int s = d.src_order[k];
     const SourceDev &S = d.sources[s];
-    const bool emit = S.E > 0 && ((n - 1) % S.E) == 0;
-    d.em_off[k] = emit ? S.ne : 0;
+    // the horizontal-motion ring, then the vertical-motion ring, each on its cadence
+    const bool emit_h = S.E > 0 && ((n - 1) % S.E) == 0;
+    const bool emit_v = S.Eh > 0 && ((n - 1) % S.Eh) == 0;
+    const bool emit = emit_h || emit_v;
+    d.em_off[k] = (emit_h ? S.ne : 0) + (emit_v ? S.ne : 0);
     if (emit) {
       const PatchDev &P = d.patches[S.patch];
       const double xs = S.x0 + S.vx * tn;
@@ -163,7 +166,8 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
   for (int k = tid; k < d.ns; k += kThreads) {
     const int s = d.src_order[k];
     const SourceDev &S = d.sources[s];
-    if (d.em_off[k]) atomicAdd(&d.ctr[((size_t)S.patch * d.nb + S.bucket) * CNT_NUM + CNT_EMIT], (unsigned long long)S.ne);
+    if (d.em_off[k])
+      atomicAdd(&d.ctr[((size_t)S.patch * d.nb + S.bucket) * CNT_NUM + CNT_EMIT], (unsigned long long)d.em_off[k]);
   }
   __syncthreads();
   const int32_t tot_inj = block_scan_excl(d.inj_off, ns_inj, s_tmp);
@@ -368,8 +372,13 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
         if (d.em_off[mid] <= gi) lo = mid; else hi = mid;
       }
       const int s = d.src_order[lo];
-      const int j = gi - d.em_off[lo];
       const SourceDev &S = d.sources[s];
+      // the source's block: its horizontal-motion ring (when emitted this
+      // step) first, then its vertical-motion ring
+      const bool emit_h = S.E > 0 && ((n - 1) % S.E) == 0;
+      int j = gi - d.em_off[lo];
+      const bool heave = !emit_h || j >= S.ne;
+      if (heave && emit_h) j -= S.ne;
       const int2 sp = d.src_pos[s];
       const int2 O = d.ring_O[S.ring0 + j];
       pid = S.patch;
@@ -379,8 +388,8 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       q.oy = sp.y + O.y;
       q.age = 0;
       q.code = j * S.a0;
-      q.meta = pack_meta(0, 1, bkt, pid, s, j);
-      q.amp = S.B * d.ring_m[S.ring0 + j];
+      q.meta = pack_meta(0, 1, bkt, pid, s, j) | (heave ? kHeaveBit : 0u);
+      q.amp = heave ? heave_amp(S, n, 0u) : S.B * d.ring_m[S.ring0 + j];
       o[0] = q;
       nout = 1;
     }

@@ -452,6 +452,8 @@ int hwo_add_source(hwo_ocean *o, const hwo_source *s, int32_t *id) {
   if (!(s->radius > 0) || !(s->draft >= 0)) return o->fail(HWO_EINVAL, "bad source radius/draft");
   if (s->ring_n < 1 || s->ring_n > kMaxRing || 128 % s->ring_n != 0)
     return o->fail(HWO_EINVAL, "ring_n must divide 128");
+  if (!(s->heave_amp >= 0) || (s->heave_amp > 0 && !(s->heave_period > 0)))
+    return o->fail(HWO_EINVAL, "bad heave amplitude/period");
   if (id) *id = (int32_t)o->sources.size();
   o->sources.push_back(*s);
   return HWO_OK;
@@ -614,6 +616,17 @@ static int build_scene_tables(hwo_ocean *o) {
     }
     for (int j = 0; j < hs.ring_n; ++j)
       o->ring_amp[(size_t)si * kMaxRing + j] = S.B * o->ring_m[(size_t)S.ring0 + j];
+    // vertical motion: a ring each time the previous one has travelled half
+    // a radius; its crests carry pi R^2 dz, shared by the n_e particles
+    S.Eh = 0;
+    S.Bh = 0.0;
+    S.hf = 0.0;
+    if (hs.heave_amp > 0.0) {
+      const double e = floor(0.5 * rb / (cb * dt));
+      S.Eh = e < 1.0 ? 1 : (int32_t)std::min(e, (double)(1 << 30));
+      S.Bh = M_PI * R * R * hs.heave_amp / ((double)hs.ring_n * rb * rb);
+      S.hf = dt / hs.heave_period;
+    }
     for (int L = 0; L < kMaxLevel; ++L) {
       const double alpha = 2.0 * M_PI / ((double)hs.ring_n * (double)ipow3(L));
       const double x = (o->sp.subdiv_frac * rb / alpha - R) / (cb * dt);
@@ -1178,7 +1191,7 @@ int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_
       const uint32_t m = r.meta;
       const int64_t age = (int64_t)(((uint32_t)step - (r.bc & 0xFFFFu)) & 0xFFFFu);
       int64_t *q = dst + 10 * k;
-      q[0] = m_patch(m); q[1] = m_bucket(m); q[2] = m_kind(m); q[3] = m_level(m);
+      q[0] = m_patch(m); q[1] = m_bucket(m); q[2] = m_kind(m) + (m_heave(m) ? 1 : 0); q[3] = m_level(m);
       q[4] = r.bc >> 16; q[5] = step - age; q[6] = r.ox; q[7] = r.oy;
       q[8] = m_src(m) == kNoSource ? -1 : (int64_t)m_src(m); q[9] = m_slot(m);
     }
@@ -1189,7 +1202,7 @@ int hwo_read_particles(hwo_ocean *o, int64_t *dst, int64_t max_recs, int64_t *n_
       const RecWide &r = h[k];
       const uint32_t m = r.meta;
       int64_t *q = dst + 10 * k;
-      q[0] = m_patch(m); q[1] = m_bucket(m); q[2] = m_kind(m); q[3] = m_level(m);
+      q[0] = m_patch(m); q[1] = m_bucket(m); q[2] = m_kind(m) + (m_heave(m) ? 1 : 0); q[3] = m_level(m);
       q[4] = r.code; q[5] = r.birth; q[6] = r.ox; q[7] = r.oy;
       q[8] = m_src(m) == kNoSource ? -1 : (int64_t)m_src(m); q[9] = m_slot(m);
     }
@@ -1214,14 +1227,16 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
   host.resize(rs * (size_t)std::max<int64_t>(n, 1));
   for (int64_t k = 0; k < n; ++k) {
     const int64_t *q = recs + 10 * k;
-    if (q[0] != patch || q[1] < 0 || q[1] >= o->nb || q[4] < 0 || q[4] >= kNCode || q[3] < 0 || q[3] > kMaxLevel ||
-        q[5] > step || step - q[5] > kAgeMax)
+    if (q[0] != patch || q[1] < 0 || q[1] >= o->nb || q[2] < 0 || q[2] > 2 || q[4] < 0 || q[4] >= kNCode ||
+        q[3] < 0 || q[3] > kMaxLevel || q[5] > step || step - q[5] > kAgeMax)
       return o->fail(HWO_EINVAL, "bad particle record");
-    if (q[2] == 1 && (q[8] < 0 || q[8] >= d.ns || q[9] < 0 || q[9] >= o->sdev[q[8]].ne))
+    const bool ring = q[2] >= 1;
+    if (ring && (q[8] < 0 || q[8] >= d.ns || q[9] < 0 || q[9] >= o->sdev[q[8]].ne))
       return o->fail(HWO_EINVAL, "bad ring particle record");
-    const uint32_t src = q[2] == 1 ? (uint32_t)q[8] : kNoSource;
-    const uint32_t meta = pack_meta((uint32_t)q[3], (uint32_t)q[2], (uint32_t)q[1], (uint32_t)q[0], src,
-                                    q[2] == 1 ? (uint32_t)q[9] : 0u);
+    if (q[2] == 2 && o->sdev[q[8]].Eh == 0) return o->fail(HWO_EINVAL, "vertical-motion ring of a source without heave");
+    const uint32_t src = ring ? (uint32_t)q[8] : kNoSource;
+    const uint32_t meta = pack_meta((uint32_t)q[3], ring ? 1u : 0u, (uint32_t)q[1], (uint32_t)q[0], src,
+                                    ring ? (uint32_t)q[9] : 0u) | (q[2] == 2 ? kHeaveBit : 0u);
     if (d.compact) {
       RecCompact r;
       r.ox = (int32_t)q[6]; r.oy = (int32_t)q[7];
@@ -1234,6 +1249,13 @@ int hwo_test_splat(hwo_ocean *o, int32_t patch, const int64_t *recs, int64_t n, 
       r.meta = meta;
       float amp;
       if (q[2] == 0) amp = P.A[q[1]] * (o->afac.empty() ? 1.f : o->afac[(size_t)q[1] * kNCode + q[4]]);
+      else if (q[2] == 2) {
+        const SourceDev &S = o->sdev[q[8]];
+        const double T = o->sources[q[8]].heave_period;
+        const double z0 = sin(2.0 * M_PI * ((double)(q[5] - S.Eh) * o->cfg.dt) / T);
+        const double z1 = sin(2.0 * M_PI * ((double)q[5] * o->cfg.dt) / T);
+        amp = (float)(S.Bh * (z0 - z1) / std::pow(3.0, (double)q[3]));
+      }
       else {
         const SourceDev &S = o->sdev[q[8]];
         amp = S.B * o->ring_m[S.ring0 + q[9]];

@@ -450,13 +450,15 @@ __device__ __forceinline__ DecIn dec_load(const Dev &d, const Rec &r, int64_t n,
   const Part q = RecIO<Rec>::unpack(r, n);
   if ((int)m_bucket(q.meta) != b || (int)m_patch(q.meta) != patch) return o;
   const bool ring = m_kind(q.meta) != 0;
-  o.flags = 1u | (ring ? 2u : 0u) | (m_level(q.meta) << 2);
+  const bool heave = m_heave(q.meta);
+  o.flags = 1u | (ring ? 2u : 0u) | (m_level(q.meta) << 2) | (heave ? 32u : 0u) | (m_src(q.meta) << 8);
   o.ox = q.ox;
   o.oy = q.oy;
   o.age = q.age;
   o.v = velocity(d, b, q.code, !ring);
   o.code = q.code;
   if (RecIO<Rec>::kHasAmp) o.f = q.amp;
+  else if (heave) o.f = 0.f;   // computed from the source's motion in dec_point
   else if (ring) o.f = d.ring_amp[m_src(q.meta) * kMaxRing + m_slot(q.meta)];
   else if (d.afac) o.f = d.afac[b * kNCode + q.code];
   return o;
@@ -465,8 +467,8 @@ __device__ __forceinline__ DecIn dec_load(const Dev &d, const Rec &r, int64_t n,
 // Crest (cx, cy) in tile cells and signed amplitude A (0: nothing to splat);
 // the trough lies rc u behind the crest.
 template <class Rec>
-__device__ __forceinline__ void dec_point(const DecIn &i, const TileGeom &T, float Ab, float &cx, float &cy,
-                                          float &A) {
+__device__ __forceinline__ void dec_point(const Dev &d, int64_t n, const DecIn &i, const TileGeom &T, float Ab,
+                                          float &cx, float &cy, float &A) {
   const int64_t px = (int64_t)i.ox + (((int64_t)i.age * i.v.x) >> 12);
   const int64_t py = (int64_t)i.oy + (((int64_t)i.age * i.v.y) >> 12);
   cx = (float)(px - T.X0) * T.inv_dxu;
@@ -475,6 +477,7 @@ __device__ __forceinline__ void dec_point(const DecIn &i, const TileGeom &T, flo
   const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;
   if (!(i.flags & 1u)) A = 0.f;
   else if (RecIO<Rec>::kHasAmp) A = i.f;
+  else if (i.flags & 32u) A = heave_amp(d.sources[(i.flags >> 8) & 127u], n - i.age, lv);
   else if (i.flags & 2u) A = i.f * inv3;
   else A = Ab * i.f;
 }
@@ -690,7 +693,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
       // ---- this batch's points: a crest and a trough per lane
       const int b = b0;
       float cx, cy, A;
-      dec_point<Rec>(in0, T, P.A[b], cx, cy, A);
+      dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A);
       const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
       const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
       const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches

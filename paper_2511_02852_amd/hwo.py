@@ -57,7 +57,8 @@ class HwoPlan(C.Structure):
 
 class HwoSource(C.Structure):
     _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
-                ("radius", C.c_double), ("draft", C.c_double), ("ring_n", C.c_int32), ("patch", C.c_int32)]
+                ("radius", C.c_double), ("draft", C.c_double), ("ring_n", C.c_int32), ("patch", C.c_int32),
+                ("heave_amp", C.c_double), ("heave_period", C.c_double)]
 
 
 class HwoError(RuntimeError):
@@ -202,7 +203,8 @@ class Ocean:
             hp = HwoPatch(p.anchor_x, p.anchor_y, p.nx, p.ny, p.dx, p.eta, p.blend_band, p.follow)
             self._check(self.L.hwo_add_patch(self.h, C.byref(hp), C.byref(pid)))
         for s in scene.sources:
-            hs_ = HwoSource(s.x0, s.y0, s.vx, s.vy, s.radius, s.draft, s.ring_n, s.patch)
+            hs_ = HwoSource(s.x0, s.y0, s.vx, s.vy, s.radius, s.draft, s.ring_n, s.patch,
+                            float(getattr(s, "heave_amp", 0.0)), float(getattr(s, "heave_period", 0.0)))
             self._check(self.L.hwo_add_source(self.h, C.byref(hs_), C.byref(pid)))
         b = bins if bins is not None else scene.bins
         if b is not None:
