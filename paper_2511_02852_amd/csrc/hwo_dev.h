@@ -88,6 +88,7 @@ struct PatchDev {
   float A[kMaxBuckets];        // boundary amplitude per bucket
   uint64_t Rx[kMaxBuckets], Ry[kMaxBuckets];
   int32_t binu[kMaxBuckets];   // bin edge (position units)
+  uint64_t binm[kMaxBuckets];  // ceil(2^64 / binu): x / binu = high word of binm * x for any 32-bit x
   int32_t nbx[kMaxBuckets], nby[kMaxBuckets], binbase[kMaxBuckets];
   // texel-layer synthesis: per bucket, the x-filtered layer (rows of the
   // patch plus lay_R cells on every side, patch columns, row-major)
@@ -175,10 +176,12 @@ struct Dev {
   const int2 *ring_O;          // [sum ne] ring offsets (units)
   Globals *glob;
   StepPatch *sp;
+  StepPatch *sp_next;          // windows of the next step (the scatter counts the next step's bins)
   int32_t *inj_off;            // [n_inj_slots + 1]
   int32_t *em_off;             // [ns + 1]
   int2 *src_pos;               // [ns] source position (units, patch frame)
   unsigned long long *ctr;     // [np][nb][CNT_NUM]
+  unsigned long long *ctr_next;   // [np][nb][CNT_NUM] the next step's subdivided / died counts so far
   int32_t *hist, *off, *cur, *bsum;
   void *S0, *S1;               // particle buffers; step n reads S[(n-1)&1], writes S[n&1]
   const float2 *h0T;           // [N][N] h0 transposed: row = kx index
@@ -389,6 +392,9 @@ void launch_params(const Dev &d, hipStream_t st);
 // Windows of every patch at the current step (no advance).
 void launch_windows(const Dev &d, hipStream_t st);
 void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st);
+int update_blocks_per_cu(bool compact, bool scatter);
+// The next step's histogram and counters of the current buffer (after a restore).
+void launch_predict(const Dev &d, int p0, int p1, int grid, hipStream_t st);
 void launch_scan(const Dev &d, int bin_lo, int bin_hi, bool first, bool last, hipStream_t st);
 void launch_splat_plan(const Dev &d, int t0, int ntiles, int items_target, hipStream_t st);
 void launch_splat_tiles(const Dev &d, int t0, int ntiles, int grid, hipStream_t st);

@@ -68,17 +68,25 @@ __device__ int32_t block_scan_excl(int32_t *a, int len, int32_t *s_w /* kThreads
 // whole cells on the source's FP64 position), its background offsets and the
 // range of its previous particles in the input buffer.  The injection and
 // emission ranges are left to the caller.
-__device__ void patch_window(const Dev &d, int p, int64_t n, StepPatch &W) {
-  const double tn = (double)n * d.dt;
+// Window origin (cells) of patch p at step n.
+__device__ __forceinline__ void window_origin(const Dev &d, int p, int64_t n, int64_t &wx, int64_t &wy) {
   const PatchDev &P = d.patches[p];
-  int64_t wx = 0, wy = 0;
+  wx = 0;
+  wy = 0;
   if (P.follow >= 0) {
+    const double tn = (double)n * d.dt;
     const SourceDev &S = d.sources[P.follow];
     const double xs = S.x0 + S.vx * tn;
     const double ys = S.y0 + S.vy * tn;
     wx = round_away((xs - P.ax) / P.dx) - P.nx / 2;
     wy = round_away((ys - P.ay) / P.dx) - P.ny / 2;
   }
+}
+
+__device__ void patch_window(const Dev &d, int p, int64_t n, StepPatch &W) {
+  const PatchDev &P = d.patches[p];
+  int64_t wx, wy;
+  window_origin(d, p, n, wx, wy);
   W.wx = (int32_t)wx;
   W.wy = (int32_t)wy;
   // keep every window (with a 64 m margin) inside the int32 position range
@@ -108,6 +116,9 @@ __global__ __launch_bounds__(kThreads) void k_windows(Dev d) {
     StepPatch W = d.sp[p];
     patch_window(d, p, n, W);
     d.sp[p] = W;
+    StepPatch Wn = W;
+    patch_window(d, p, n + 1, Wn);
+    d.sp_next[p] = Wn;
   }
 }
 
@@ -125,11 +136,18 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
   const int64_t n = s_n;
   const double tn = (double)n * d.dt;
 
-  // windows, background offsets, previous-particle ranges
+  // windows, background offsets, previous-particle ranges; the windows of
+  // the next step for the scatter's histogram of it
   for (int p = tid; p < d.np; p += kThreads) {
     StepPatch W;
     patch_window(d, p, n, W);
     d.sp[p] = W;
+    int64_t wx, wy;
+    window_origin(d, p, n + 1, wx, wy);   // only the origin is used for the next step's bins
+    StepPatch Wn = W;
+    Wn.wx = (int32_t)wx;
+    Wn.wy = (int32_t)wy;
+    d.sp_next[p] = Wn;
   }
 
   // injection counts per (patch, bucket, pair), in that order
@@ -198,9 +216,9 @@ __device__ __forceinline__ int32_t survive_key(const Dev &d, const PatchDev &P, 
   const int64_t lox = (int64_t)W.wx * P.dxu - m, hix = (int64_t)(W.wx + P.nx) * P.dxu + m;
   const int64_t loy = (int64_t)W.wy * P.dxu - m, hiy = (int64_t)(W.wy + P.ny) * P.dxu + m;
   if (px < lox || px > hix || py < loy || py > hiy) return -1;
-  const uint32_t binu = (uint32_t)P.binu[bucket];
-  const uint32_t bx = (uint32_t)(px - lox) / binu;
-  const uint32_t by = (uint32_t)(py - loy) / binu;
+  const uint64_t binm = P.binm[bucket];   // 1 / bin edge, 64.64 fixed point rounded up
+  const uint32_t bx = (uint32_t)__umul64hi(binm, (uint64_t)(uint32_t)(px - lox));
+  const uint32_t by = (uint32_t)__umul64hi(binm, (uint64_t)(uint32_t)(py - loy));
   return P.binbase[bucket] + (int32_t)(by * (uint32_t)P.nbx[bucket] + bx);
 }
 
@@ -246,7 +264,77 @@ __device__ __forceinline__ void wave_add(unsigned long long *ctr, int key, uint3
   }
 }
 
-template <class Rec, bool kScatter>
+// Subdivision (at most one level per step): a ring particle whose age has
+// reached its source's split age for its level becomes three, at codes
+// c - a0/3^(L+1), c, c + a0/3^(L+1), each a third of the amplitude.  o[0] is
+// the particle itself (or the middle child).  Returns the number of outputs.
+__device__ __forceinline__ int subdivide(const Dev &d, const Part &q, Part o[3]) {
+  o[0] = q;
+  const uint32_t lev = m_level(q.meta);
+  if (m_kind(q.meta) != 1 || (int)lev >= d.lmax) return 1;
+  const SourceDev &S = d.sources[m_src(q.meta)];
+  if (q.age < S.T[lev]) return 1;
+  int off = S.a0;
+  for (uint32_t l = 0; l <= lev; ++l) off /= 3;
+  o[0].meta = (q.meta & ~7u) | (lev + 1);
+  o[0].amp = q.amp * (1.0f / 3.0f);
+  o[1] = o[0];
+  o[2] = o[0];
+  o[1].code = (q.code - off + kNCode) % kNCode;
+  o[2].code = (q.code + off) % kNCode;
+  return 3;
+}
+
+// The next step's bin histogram and subdivided/died counters of a particle
+// as it stands after step n (its outputs at step n + 1: subdivision at age
+// + 1, survival against the window of step n + 1).  Adding them while the
+// particle is written saves the next step a pass over every record.  All
+// lanes of the wavefront call this (ballots inside).
+__device__ __forceinline__ void predict_next(const Dev &d, const Part &q, bool valid) {
+  Part c[3];
+  int32_t key[3] = {-1, -1, -1};
+  int pid = 0, bkt = 0;
+  bool sub = false;
+  uint32_t ndead = 0;
+  if (valid) {
+    Part q1 = q;
+    q1.age = q.age + 1;
+    const int nc = subdivide(d, q1, c);
+    sub = nc == 3;
+    pid = (int)m_patch(q.meta);
+    bkt = (int)m_bucket(q.meta);
+    const PatchDev &P = d.patches[pid];
+    const StepPatch W = d.sp_next[pid];
+    const bool boundary = m_kind(q.meta) == 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if (r < nc) {
+        int64_t px, py;
+        key[r] = survive_key(d, P, W, bkt, c[r].code, boundary, c[r].ox, c[r].oy, c[r].age, px, py);
+        if (key[r] < 0) ++ndead;
+      }
+    }
+  }
+  const int cbase = (pid * d.nb + bkt) * CNT_NUM;
+  wave_add(d.ctr_next, sub ? cbase + CNT_SUB : -1, 1u);
+  wave_add(d.ctr_next, ndead ? cbase + CNT_DIED : -1, ndead);
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    if (r > 0 && __ballot(key[r] >= 0) == 0ull) continue;
+    const Run run = wave_runs(key[r]);
+    if (run.is_head) atomicAdd(&d.hist[key[r]], run.len);
+  }
+}
+
+// Modes of the update pass.
+//   kCountNew   the bin histogram of the particles created this step
+//               (injected and emitted); the previous step's scatter already
+//               counted the particles that carry over
+//   kScatter    all particles of the step in bin order into the output
+//               buffer, and the next step's histogram of what was written
+enum { kCountNew = 0, kScatter = 1 };
+
+template <class Rec, int kMode>
 __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   const int64_t n = d.glob->n;
   const Rec *__restrict__ Sin = (const Rec *)(((n - 1) & 1) ? d.S1 : d.S0);
@@ -256,6 +344,7 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   const int in0 = A.inj_lo, ninj = B.inj_hi - A.inj_lo;
   const int em0 = A.em_lo, nem = B.em_hi - A.em_lo;
   const int total = nex + ninj + nem;
+  const int kbeg = kMode == kCountNew ? nex : 0;   // counting skips the carried-over particles
   const int lane = (int)__lane_id();
   // injection slot offsets and direction CDFs, copied to LDS by the blocks
   // that hold new boundary particles (their searches then stay in LDS)
@@ -267,11 +356,24 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
   const int stride = (int)gridDim.x * kThreads;
   Rec rec_next;
   {
-    const int k0 = (int)blockIdx.x * kThreads + (int)threadIdx.x;
+    const int k0 = kbeg + (int)blockIdx.x * kThreads + (int)threadIdx.x;
     if (k0 < nex) rec_next = Sin[ex0 + k0];
   }
+  if (kMode == kCountNew && p0 == 0) {
+    // this step's subdivided and died counts of the carried-over particles,
+    // found by the previous step's scatter (before this step's scatter
+    // starts on the next step's)
+    for (int q = (int)blockIdx.x * kThreads + (int)threadIdx.x; q < d.np * d.nb * CNT_NUM;
+         q += (int)gridDim.x * kThreads) {
+      const unsigned long long v = d.ctr_next[q];
+      if (v) {
+        atomicAdd(&d.ctr[q], v);
+        d.ctr_next[q] = 0ull;
+      }
+    }
+  }
 
-  for (int base = blockIdx.x * kThreads; base < total; base += stride) {
+  for (int base = kbeg + (int)blockIdx.x * kThreads; base < total; base += stride) {
     const int k = base + (int)threadIdx.x;
     const Rec rec = rec_next;
     if (k + stride < nex) rec_next = Sin[ex0 + k + stride];
@@ -293,24 +395,8 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
       if (!RecIO<Rec>::kHasAmp && q.age == 0) q.age = 65536;   // 16-bit birth wrapped: expired
       pid = (int)m_patch(q.meta);
       bkt = (int)m_bucket(q.meta);
-      o[0] = q;
-      nout = 1;
-      const uint32_t lev = m_level(q.meta);
-      if (m_kind(q.meta) == 1 && (int)lev < d.lmax) {
-        const SourceDev &S = d.sources[m_src(q.meta)];
-        if (q.age >= S.T[lev]) {
-          int off = S.a0;
-          for (uint32_t l = 0; l <= lev; ++l) off /= 3;
-          o[0].meta = (q.meta & ~7u) | (lev + 1);
-          o[0].amp = q.amp * (1.0f / 3.0f);
-          o[1] = o[0];
-          o[2] = o[0];
-          o[1].code = (q.code - off + kNCode) % kNCode;
-          o[2].code = (q.code + off) % kNCode;
-          nout = 3;
-          subdivided = true;
-        }
-      }
+      nout = subdivide(d, q, o);
+      subdivided = nout == 3;
     } else if (k < nex + ninj) {
       // ---- a new boundary particle
       const int gi = in0 + (k - nex);
@@ -406,17 +492,18 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
         }
       }
     }
-    if (!kScatter) {
+    if (kMode == kCountNew) {
+      // only new particles here: none subdivides, some die at once
       const int cbase = (pid * d.nb + bkt) * CNT_NUM;
-      wave_add(d.ctr, subdivided ? cbase + CNT_SUB : -1, 1u);
       wave_add(d.ctr, ndead ? cbase + CNT_DIED : -1, ndead);
     }
     // merge runs of equal keys, one atomic per run
+    bool written[3] = {false, false, false};
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
       if (r > 0 && __ballot(key[r] >= 0) == 0ull) continue;
       const Run run = wave_runs(key[r]);
-      if (!kScatter) {
+      if (kMode == kCountNew) {
         if (run.is_head) atomicAdd(&d.hist[key[r]], run.len);
       } else {
         int32_t basepos = 0;
@@ -424,14 +511,41 @@ __global__ __launch_bounds__(kThreads) void k_update(Dev d, int p0, int p1) {
         basepos = __shfl(basepos, run.head);
         if (key[r] >= 0) {
           const int32_t slotpos = basepos + run.rank;
-          if (slotpos < d.cap)
+          if (slotpos < d.cap) {
             RecIO<Rec>::store(Sout, slotpos, o[r], n);
-          else
+            written[r] = true;
+          } else {
             atomicAdd(&d.glob->dropped, 1ull);
+          }
         }
       }
     }
+    if (kMode == kScatter) {
+      // this step's subdivided / died counts of carried-over particles were
+      // added by the previous step's scatter; the next step's are added here
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (r > 0 && __ballot(written[r]) == 0ull) continue;
+        predict_next(d, o[r], written[r]);
+      }
+    }
     (void)lane;
+  }
+}
+
+// The next step's histogram and counters of the particles in the current
+// buffer (after a restore, when no scatter has predicted them).
+template <class Rec>
+__global__ __launch_bounds__(kThreads) void k_predict(Dev d, int p0, int p1) {
+  const int64_t n = d.glob->n;
+  const Rec *__restrict__ S = (const Rec *)((n & 1) ? d.S1 : d.S0);
+  const int lo = min(d.off[d.patches[p0].bin_lo], d.cap), hi = min(d.off[d.patches[p1 - 1].bin_hi], d.cap);
+  for (int base = lo + (int)blockIdx.x * kThreads; base < hi; base += (int)gridDim.x * kThreads) {   // block-uniform
+    const int k = base + (int)threadIdx.x;
+    Part q;
+    const bool valid = k < hi;
+    if (valid) q = RecIO<Rec>::unpack(S[k], n);   // age 0: born this step
+    predict_next(d, q, valid);
   }
 }
 
@@ -544,12 +658,31 @@ void launch_windows(const Dev &d, hipStream_t st) {
 
 void launch_update(const Dev &d, int p0, int p1, bool scatter, int grid, hipStream_t st) {
   if (d.compact) {
-    if (scatter) hipLaunchKernelGGL((k_update<RecCompact, true>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
-    else hipLaunchKernelGGL((k_update<RecCompact, false>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+    if (scatter) hipLaunchKernelGGL((k_update<RecCompact, kScatter>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+    else hipLaunchKernelGGL((k_update<RecCompact, kCountNew>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
   } else {
-    if (scatter) hipLaunchKernelGGL((k_update<RecWide, true>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
-    else hipLaunchKernelGGL((k_update<RecWide, false>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+    if (scatter) hipLaunchKernelGGL((k_update<RecWide, kScatter>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+    else hipLaunchKernelGGL((k_update<RecWide, kCountNew>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
   }
+}
+
+// Blocks of the update pass resident per compute unit (the persistent grid
+// must fit in one round, or its last blocks would run after the others).
+int update_blocks_per_cu(bool compact, bool scatter) {
+  int nb = 0;
+  hipError_t e;
+  if (compact)
+    e = scatter ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update<RecCompact, kScatter>, kThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update<RecCompact, kCountNew>, kThreads, 0);
+  else
+    e = scatter ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update<RecWide, kScatter>, kThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_update<RecWide, kCountNew>, kThreads, 0);
+  return (e == hipSuccess && nb > 0) ? nb : 4;
+}
+
+void launch_predict(const Dev &d, int p0, int p1, int grid, hipStream_t st) {
+  if (d.compact) hipLaunchKernelGGL((k_predict<RecCompact>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
+  else hipLaunchKernelGGL((k_predict<RecWide>), dim3(grid), dim3(kThreads), 0, st, d, p0, p1);
 }
 
 void launch_scan(const Dev &d, int lo, int hi, bool first, bool last, hipStream_t st) {

@@ -101,7 +101,8 @@ struct hwo_ocean {
   std::vector<void *> allocs;
   float2 *h0T = nullptr, *tw = nullptr;
   uint32_t *cdf = nullptr, *cdfQ = nullptr;
-  int update_grid = 1024;
+  int update_grid = 1024;           // persistent grid of the counting pass (one round of resident blocks)
+  int scatter_grid = 1024;          // and of the scatter pass
   int target_blocks = 1024;        // resident splat blocks the persistent grid aims for
   int splat_grid = 0;              // persistent splat blocks launched (0: four times target_blocks)
   int items_target = 4096;          // splat work items per frame the plan aims for (beyond one per tile; set per scene)
@@ -526,6 +527,10 @@ static int build_scene_tables(hwo_ocean *o) {
       const int64_t binu = (int64_t)o->bin_cells[i] * P.dxu;
       if (binu >= ((int64_t)1 << 31)) return o->fail(HWO_EINVAL, "bin too large");
       P.binu[i] = (int32_t)binu;
+      // division by the bin edge as a multiplication (exact for every 32-bit
+      // dividend: Lemire, Kaser and Kurz, "Faster remainder by direct
+      // computation", 2019); binu >= 2 here
+      P.binm[i] = UINT64_MAX / (uint64_t)binu + 1;
       const int64_t m = o->margin[i];
       P.nbx[i] = (int32_t)(floor_div((int64_t)hp.nx * P.dxu + 2 * m, binu) + 1);
       P.nby[i] = (int32_t)(floor_div((int64_t)hp.ny * P.dxu + 2 * m, binu) + 1);
@@ -733,10 +738,12 @@ static int finalize(hwo_ocean *o) {
   const size_t rec = d.compact ? sizeof(RecCompact) : sizeof(RecWide);
   d.glob = (Globals *)o->alloc(sizeof(Globals));
   d.sp = (StepPatch *)o->alloc(sizeof(StepPatch) * std::max(np, 1));
+  d.sp_next = (StepPatch *)o->alloc(sizeof(StepPatch) * std::max(np, 1));
   d.inj_off = (int32_t *)o->alloc(sizeof(int32_t) * (d.n_inj_slots + 1));
   d.em_off = (int32_t *)o->alloc(sizeof(int32_t) * (ns + 1));
   d.src_pos = (int2 *)o->alloc(sizeof(int2) * std::max(ns, 1));
   d.ctr = (unsigned long long *)o->alloc(sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1));
+  d.ctr_next = (unsigned long long *)o->alloc(sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1));
   d.hist = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.nbins + 1));
   d.off = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.nbins + 1));
   d.cur = (int32_t *)o->alloc(sizeof(int32_t) * ((size_t)d.nbins + 1));
@@ -845,7 +852,8 @@ static int finalize(hwo_ocean *o) {
   if (!d.tile_load || !d.tile_meas || !d.tile_model || !d.tile_ratio || !d.item_base || !d.splat_ctl ||
       !d.split_tiles || !d.partials)
     return o->fail(HWO_ENOMEM, "device allocation failed");
-  if (!d.glob || !d.sp || !d.inj_off || !d.em_off || !d.src_pos || !d.ctr || !d.hist || !d.off || !d.cur ||
+  if (!d.glob || !d.sp || !d.sp_next || !d.ctr_next || !d.inj_off || !d.em_off || !d.src_pos || !d.ctr || !d.hist ||
+      !d.off || !d.cur ||
       !d.bsum || !d.S0 || !d.S1 || !d.FT || !d.H || !d.raw || !d.blend)
     return o->fail(HWO_ENOMEM, "device allocation failed");
   HWO_CHECK(hipMemsetAsync(d.glob, 0, sizeof(Globals), o->st));
@@ -854,6 +862,8 @@ static int finalize(hwo_ocean *o) {
   HWO_CHECK(hipMemsetAsync(d.splat_prof, 0, sizeof(unsigned long long) * PROF_N, o->st));
   HWO_CHECK(hipMemsetAsync(d.sp, 0, sizeof(StepPatch) * std::max(np, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.ctr, 0, sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.ctr_next, 0, sizeof(unsigned long long) * (size_t)std::max(np * nb * CNT_NUM, 1), o->st));
+  HWO_CHECK(hipMemsetAsync(d.sp_next, 0, sizeof(StepPatch) * std::max(np, 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.hist, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.off, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
   HWO_CHECK(hipMemsetAsync(d.cur, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
@@ -870,7 +880,8 @@ static int finalize(hwo_ocean *o) {
   int dev_id = 0, cus = 256;
   (void)hipGetDevice(&dev_id);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id);
-  o->update_grid = std::max(64, 6 * cus);   // six blocks per CU are resident (75 registers per lane)
+  o->update_grid = std::max(64, update_blocks_per_cu(d.compact, false) * cus);
+  o->scatter_grid = std::max(64, update_blocks_per_cu(d.compact, true) * cus);
   o->target_blocks = std::max(64, 4 * cus);
   if (o->cfg.batched) {
     o->fused = bin_plan_fits(d.nbins, d.ntiles, d.nb);
@@ -899,7 +910,7 @@ static void launch_stage(hwo_ocean *o, int stage, const PatchArg *g) {
     case ST_FFT_B: launch_fft_b(d, o->st); break;
     case ST_COUNT: launch_update(d, g->p0, g->p1, false, o->update_grid, o->st); break;
     case ST_SCAN: launch_scan(d, g->b0, g->b1, g->first, g->last, o->st); break;
-    case ST_SCATTER: launch_update(d, g->p0, g->p1, true, o->update_grid, o->st); break;
+    case ST_SCATTER: launch_update(d, g->p0, g->p1, true, o->scatter_grid, o->st); break;
     case ST_PLAN: launch_splat_plan(d, g->t0, g->t1 - g->t0, o->items_target, o->st); break;
     case ST_SPLAT:
       launch_splat_tiles(d, g->t0, g->t1 - g->t0,
@@ -1421,9 +1432,14 @@ int hwo_restore(hwo_ocean *o, const void *src, int64_t src_bytes) {
   HWO_CHECK(hipMemcpyAsync(d.tile_ratio, p, sizeof(float) * (size_t)d.ntiles, hipMemcpyHostToDevice, o->st));
   p += sizeof(float) * (size_t)d.ntiles;
   if (hd.n_live > 0) HWO_CHECK(hipMemcpyAsync(S, p, rb * (size_t)hd.n_live, hipMemcpyHostToDevice, o->st));
-  // windows of the restored step, for probes and test splats before the next step
+  // windows of the restored step (for probes and test splats before the next
+  // step) and of the next one; the next step's histogram and counts of the
+  // restored particles, which a scatter would have found
   if (d.np > 0) {
     launch_windows(d, o->st);
+    HWO_CHECK(hipMemsetAsync(d.hist, 0, sizeof(int32_t) * ((size_t)d.nbins + 1), o->st));
+    HWO_CHECK(hipMemsetAsync(d.ctr_next, 0, nctr, o->st));
+    launch_predict(d, 0, d.np, o->update_grid, o->st);
     HWO_CHECK(hipGetLastError());
   }
   HWO_CHECK(hipStreamSynchronize(o->st));
