@@ -87,6 +87,13 @@ typedef struct {
                                for |d| < r; 1 radial W(|d|) with the same profile.
                                The radial kernel needs synth 0 (the texel passes
                                are separable); synth 1 with kernel 1 is HWO_EINVAL. */
+    int32_t fft_mfma16;     /* 1: the first stage of every background FFT row
+                               (N >= 1024) is a radix-16 DFT on the matrix cores
+                               with split bf16 (hi + lo) operands and FP32
+                               accumulation; 0 (default): the FP32 radix-8/4/2
+                               stages only.  An option for measurement: it is
+                               no faster (the passes are bound by HBM) and its
+                               error is about ten times larger. */
 } hwo_config;
 
 /* Spectrum and bucket parameters (Sec 3.1, Sec 3.3). */

@@ -128,6 +128,116 @@ __device__ __forceinline__ void fft_lds(float2 *buf, int t, const float2 *__rest
   if (rem == 1) fft_stage<N, T, 2>(buf, t, Ns, tw);
 }
 
+// ---- radix-16 first stage on the matrix cores (optional)
+// The first stage of the Stockham FFT (no twiddles) is a batch of 16-point
+// DFTs, Y = F X with F[m][r] = e^{+2 pi i m r / 16}, i.e. in real form
+// [Yr; Yi] = [[Fr, -Fi], [Fi, Fr]] [Xr; Xi]: for 32 butterflies at a time a
+// 32 x 32 by 32 x 32 product, two 32x32x16 bf16 matrix-core products per
+// operand pair.  FP32 operands are split into bf16 hi + lo parts; hi hi,
+// hi lo and lo hi products are accumulated in FP32 (lo lo, ~2^-16 relative,
+// is dropped).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+// Butterflies j0 .. j0 + 31 (input x[j + r N/16], output y[16 j + m]) of one
+// transform held in buf; the outputs are returned in registers (lane l: the
+// m = 4 (l / 32) + {0..3} and 8 + 4 (l / 32) + {0..3} outputs of butterfly
+// j0 + l % 32, real parts in d[0..7], imaginary in d[8..15]) so that the
+// caller can write them after every wave has read its inputs.
+template <int N>
+__device__ __forceinline__ f32x16v dft16_mfma(const float2 *buf, int j0, int lane) {
+  const int j = j0 + (lane & 31), kb = 8 * (lane >> 5);   // butterfly; first r of the lane's K slice
+  // operands: A = the DFT matrix (rows i = m or 16 + m, columns r), split
+  bf16x8 a0h, a0l, a1h, a1l, xrh, xrl, xih, xil;
+  const int i = lane & 31, m = i & 15;
+  const bool top = i < 16;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int r = kb + q;
+    const float ph = (float)((m * r) & 15) * (1.0f / 16.0f);   // revolutions
+    const float c = __builtin_amdgcn_cosf(ph), s = __builtin_amdgcn_sinf(ph);
+    const float v0 = top ? c : s, v1 = top ? -s : c;   // columns r of [Fr; Fi] and [-Fi; Fr]
+    const __bf16 h0 = (__bf16)v0, h1 = (__bf16)v1;
+    a0h[q] = h0;
+    a0l[q] = (__bf16)(v0 - (float)h0);
+    a1h[q] = h1;
+    a1l[q] = (__bf16)(v1 - (float)h1);
+    const float2 x = buf[j + r * (N / 16)];
+    const __bf16 xr = (__bf16)x.x, xi = (__bf16)x.y;
+    xrh[q] = xr;
+    xrl[q] = (__bf16)(x.x - (float)xr);
+    xih[q] = xi;
+    xil[q] = (__bf16)(x.y - (float)xi);
+  }
+  f32x16v acc;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, xrh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0h, xrl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0l, xrh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, xih, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1h, xil, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1l, xih, acc, 0, 0, 0);
+  return acc;
+}
+
+// First stage (radix 16) of an N-point transform with T threads on the
+// matrix cores; every thread of the block calls it.
+template <int N, int T>
+__device__ __forceinline__ void fft_stage16_mfma(float2 *buf, int t) {
+  constexpr int G = N / 16 / 32;        // groups of 32 butterflies
+  constexpr int W = T / 64;             // wavefronts per transform
+  constexpr int PER = (G + W - 1) / W;  // groups per wavefront
+  const int w = t >> 6, lane = t & 63;
+  f32x16v out[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (w + u * W < G) out[u] = dft16_mfma<N>(buf, 32 * (w + u * W), lane);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (w + u * W < G) {
+      const int j = 32 * (w + u * W) + (lane & 31);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        // D row i = 8 (q / 4) + 4 (l / 32) + q % 4 (q < 8: real part, row i + 16: imaginary part)
+        const int mo = 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        buf[16 * j + mo] = make_float2(out[u][q], out[u][q + 8]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Full inverse FFT with the radix-16 first stage on the matrix cores, then
+// radix-8 stages and one radix-4 or radix-2 stage.
+template <int N, int T>
+__device__ __forceinline__ void fft_lds_m16(float2 *buf, int t, const float2 *__restrict__ tw) {
+  fft_stage16_mfma<N, T>(buf, t);
+  int Ns = 16;
+  constexpr int L2 = __builtin_ctz(N) - 4;
+  constexpr int n8 = L2 / 3;
+  constexpr int rem = L2 - 3 * n8;
+#pragma unroll
+  for (int s = 0; s < n8; ++s) {
+    fft_stage<N, T, 8>(buf, t, Ns, tw);
+    Ns *= 8;
+  }
+  if (rem == 2) fft_stage<N, T, 4>(buf, t, Ns, tw);
+  if (rem == 1) fft_stage<N, T, 2>(buf, t, Ns, tw);
+}
+
+template <int N, int T>
+__device__ __forceinline__ void fft_row(float2 *buf, int t, const float2 *__restrict__ tw, bool m16) {
+  if constexpr (N >= 1024 && T >= 64 && N / 512 >= T / 64) {
+    if (m16) {
+      fft_lds_m16<N, T>(buf, t, tw);
+      return;
+    }
+  }
+  fft_lds<N, T>(buf, t, tw);
+}
+
 template <int N> struct FftShape {
   static constexpr int T = (N / 8 < kThreads) ? (N / 8 < 1 ? 1 : N / 8) : kThreads;
   static constexpr int F = kThreads / T;      // transforms per block
@@ -202,7 +312,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
     for (int e = t; e < N; e += T) row[e] = make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<N, T>(row, t, d.tw);
+  fft_row<N, T>(row, t, d.tw, d.fft_mfma16 != 0);
   if (active) {
     float2 *__restrict__ out = d.FT + (size_t)field * (N / 2 + 1) * N + (size_t)mx * N;
     for (int e = t; e < N; e += T) out[e] = row[e];
@@ -254,7 +364,7 @@ __global__ __launch_bounds__(FftShapeB<N>::B) void k_fft_b(Dev d) {
   __syncthreads();
   const int f = threadIdx.x / T, t = threadIdx.x % T;
   float2 *row = buf + f * N;
-  fft_lds<N, T>(row, t, d.tw);
+  fft_row<N, T>(row, t, d.tw, d.fft_mfma16 != 0);
   float *__restrict__ ha = d.H + (size_t)blockIdx.y * N * N + (size_t)(jy0 + 2 * f) * N;
   float *__restrict__ hb = ha + N;
   for (int e = t; e < N; e += T) {

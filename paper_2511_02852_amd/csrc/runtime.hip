@@ -251,6 +251,7 @@ int hwo_create_ocean(const hwo_config *cfg, hwo_ocean **out) {
   if (cfg->bg_fields != 0 && cfg->bg_fields != 1) return HWO_EINVAL;
   if (cfg->kernel != 0 && cfg->kernel != 1) return HWO_EINVAL;
   if (cfg->kernel == 1 && cfg->synth != 0) return HWO_EINVAL;
+  if (cfg->fft_mfma16 != 0 && cfg->fft_mfma16 != 1) return HWO_EINVAL;
   if ((cfg->dev_alloc == nullptr) != (cfg->dev_free == nullptr)) return HWO_EINVAL;
   hwo_ocean *o = new hwo_ocean();
   o->cfg = *cfg;
@@ -697,6 +698,7 @@ static int finalize(hwo_ocean *o) {
   d.nb = nb;
   d.N = N;
   d.compact = o->cfg.compact ? 1 : 0;
+  d.fft_mfma16 = o->cfg.fft_mfma16 && N >= 1024 ? 1 : 0;
   d.lmax = o->lmax;
   d.n_inj_slots = np * nb * 2;
   d.g = o->cfg.g;

@@ -34,7 +34,7 @@ class HwoConfig(C.Structure):
                 ("seed", C.c_uint64), ("compact", C.c_int32), ("batched", C.c_int32), ("stream", C.c_void_p),
                 ("dev_alloc", ALLOC_FN), ("dev_free", FREE_FN), ("alloc_ctx", C.c_void_p),
                 ("max_particles", C.c_int64), ("synth", C.c_int32), ("normals", C.c_int32),
-                ("bg_fields", C.c_int32), ("kernel", C.c_int32)]
+                ("bg_fields", C.c_int32), ("kernel", C.c_int32), ("fft_mfma16", C.c_int32)]
 
 
 class HwoSpectrum(C.Structure):
@@ -161,7 +161,7 @@ class Ocean:
     """One hybrid ocean on the GPU, built from a :class:`scenes.Scene`."""
 
     def __init__(self, scene, *, compact=None, batched=None, bins=None, max_particles=0,
-                 torch_memory=True, stream=None, normals=False, bg_fields=False):
+                 torch_memory=True, stream=None, normals=False, bg_fields=False, fft_mfma16=False):
         self.L = lib()
         self.scene = scene
         self.h = C.c_void_p()
@@ -190,6 +190,7 @@ class Ocean:
         cfg.kernel = int(getattr(scene, "kernel", 0))
         cfg.normals = int(bool(normals))
         cfg.bg_fields = int(bool(bg_fields))
+        cfg.fft_mfma16 = int(bool(fft_mfma16))
         self._cfg = cfg
         self._check(self.L.hwo_create_ocean(C.byref(cfg), C.byref(self.h)))
         sp = scene.spectrum

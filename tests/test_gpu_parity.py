@@ -715,3 +715,28 @@ def test_vertical_motion_rings(form):
             f"split={int((P[(P[:, 2] == 2), 3] > 0).sum())} err={e}")
     P = o.particles()
     assert (P[:, 2] == 2).sum() > 0 and (P[(P[:, 2] == 2), 3] > 0).sum() > 0
+
+
+@pytest.mark.parametrize("N,L", [(1024, 2000.0), (2048, 4000.0), (4096, 8000.0)])
+def test_background_radix16_matrix_core_stage(N, L):
+    """The optional radix-16 first FFT stage on the matrix cores (split bf16
+    operands, FP32 accumulation): the background within the height tolerance
+    of the oracle (its error is reported next to that of the FP32 stages),
+    and both passes timed back to back for the keep/drop comparison."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.Scene(name="bg16", fft_n=N, fft_L=L, seed=5, spectrum=scenes.Spectrum(U10=15.0))
+    o = oracle.Oracle(s)
+    res = {}
+    for m16 in (False, True):
+        g = hwo.Ocean(s, fft_mfma16=m16)
+        g.step(23)
+        if m16:
+            o.step(23)
+        H = o.background() if m16 else None
+        res[m16] = (g.background(), g.time_stage("fft_a", 20), g.time_stage("fft_b", 20))
+        g.close()
+    H = o.background()
+    e32, e16 = rel_rms(res[False][0], H), rel_rms(res[True][0], H)
+    say(f"N={N}: FP32 stages err {e32:.2e} pass A {res[False][1] * 1e3:.1f} us pass B {res[False][2] * 1e3:.1f} us; "
+        f"matrix-core radix 16 err {e16:.2e} pass A {res[True][1] * 1e3:.1f} us pass B {res[True][2] * 1e3:.1f} us")
+    assert e32 <= TOL and e16 <= TOL
