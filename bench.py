@@ -81,7 +81,7 @@ def algorithmic(scene, rec_bytes, n_live):
     return {
         "fft_a": N * N * 8 + half * 8,            # h0 read once, half-plane write
         "fft_b": half * 8 + N * N * 4,            # half-plane read, H write
-        "count": n_live * rec_bytes,              # every record read once
+        "count": 0,                               # new particles only: no records read or written
         "scatter": 2 * n_live * rec_bytes,        # read once, written once
         "splat": n_live * rec_bytes + cells * 8,  # records once, two maps written
     }
@@ -127,8 +127,8 @@ def layer_work(ocean, scene, rec_bytes, n_live):
     return {"deposit_x": (fx, bx), "filter_y": (fy, by), "layer_sum": (0.0, bs)}
 
 
-DOM_KERNEL = {"splat": "k_splat<RecCompact, false>", "fft_a": "k_fft_a", "fft_b": "k_fft_b",
-              "count": "k_update<RecCompact, false>", "scatter": "k_update<RecCompact, true>",
+DOM_KERNEL = {"splat": "k_splat<RecCompact, false, false>", "fft_a": "k_fft_a", "fft_b": "k_fft_b",
+              "count": "k_update<RecCompact, 0>", "scatter": "k_update<RecCompact, 1>",
               "deposit_x": "k_deposit_x<RecCompact>", "filter_y": "k_filter_y", "layer_sum": "k_layer_sum"}
 
 
@@ -144,7 +144,7 @@ def measured_traffic(config, dom, radial=False):
     e = json.load(open(path)).get(config)
     name = DOM_KERNEL.get(dom)
     if radial and dom == "splat":
-        name = "k_splat<RecCompact, true>"
+        name = "k_splat<RecCompact, true, false>"
     if not e or e.get("kernel") != name:
         return None
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in e["sources"])).hexdigest()
@@ -171,14 +171,17 @@ def copy_bandwidth(mib=512, reps=10):
     return 2.0 * mib * (1 << 20) / (ms * 1e-3) / 1e9
 
 
-def splat_bucket_report(prof, splat_ms, ocean, scene, rec_bytes):
+def splat_bucket_report(prof, splat_ms, ocean, scene, rec_bytes, launches):
     """Per-bucket time of the splat from its in-kernel profile and the
     binding roof of each bucket.  A bucket's time is its share of the
     wavefront ticks (its footprints plus its share of record decoding, by
     points visited) times the splat's time per launch; its algorithmic work
     is its records read once (bytes) and two flops per cell of every crest
     and trough footprint (2 r / dx)^2 (FP32 matrix flops); the binding roof
-    is the one whose floor time is larger, and frac = floor / time."""
+    is the one whose floor time is larger, and frac = floor / time.  The
+    profile holds `launches` launches; points visited are two per record
+    entry a tile reads (records near a tile's edge are read by every tile
+    their footprints reach)."""
     nb = scene.spectrum.n_buckets
     r = ocean.buckets()[:, 2]
     live = np.zeros(nb)
@@ -199,7 +202,8 @@ def splat_bucket_report(prof, splat_ms, ocean, scene, rec_bytes):
         t_hbm, t_mfma = byts / (HBM_PEAK_GBS * 1e9), flops / (FP32_PEAK_TFLOPS * 1e12)
         bound = "mfma" if t_mfma > t_hbm else "hbm"
         rows.append({"bucket": b, "r_cells": round(float(r[b] / min(P.dx for P in scene.patches)), 2),
-                     "live": int(live[b]), "points_visited_per_launch": int(pts[b]),
+                     "live": int(live[b]), "points_visited_per_launch": int(pts[b] / launches),
+                     "record_reads_per_particle": round(float(pts[b] / launches / 2.0 / max(live[b], 1.0)), 3),
                      "share": round(float(share), 4), "ms": round(t * 1e3, 5), "bound": bound,
                      "frac": round(max(t_hbm, t_mfma) / t, 5) if t > 0 else None})
     return {"buckets": rows,
@@ -466,7 +470,7 @@ def main():
     splats_per_s = live_t / (splat_ms * 1e-3) if splat_ms > 0 else None
     splat_buckets = None
     if prof is not None:
-        splat_buckets = splat_bucket_report(prof, per_launch["splat"], prof_live, scene, g.record_bytes)
+        splat_buckets = splat_bucket_report(prof, per_launch["splat"], prof_live, scene, g.record_bytes, K)
         prof_live.close()
         log("[bench] splat per bucket (share, frac of binding roof): " +
             ", ".join(f"b{r['bucket']}={r['share']:.3f}/{r['frac']}" for r in splat_buckets["buckets"]))
@@ -511,7 +515,7 @@ def main():
     # achieved algorithmic bandwidth of the bandwidth-bound kernels, and the
     # copy bandwidth of this device as a second reference
     kernel_gbps = {k: round(alg[k] / (per_launch[k] * 1e-3) / 1e9, 1)
-                   for k in ("fft_a", "fft_b", "count", "scatter") if per_launch.get(k, 0.0) > 0}
+                   for k in ("fft_a", "fft_b", "scatter") if per_launch.get(k, 0.0) > 0}
     copy_gbs = copy_bandwidth()
 
     if args.copy_mb > 0:

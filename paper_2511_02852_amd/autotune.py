@@ -131,10 +131,17 @@ def tune(scene, preroll: int, cache: Optional[str] = None, reps: int = 8, frames
     for bins in cands:
         g = hwo.Ocean(scene.replace(bins=bins), compact=True, batched=True)
         _spin(g, preroll)
+        # frames with the starting partition, then with the searched one: the
+        # search times the splat alone, so its pick is kept only when whole
+        # frames are faster with it too
+        plan0 = g.get_plan()
+        ms0 = _time_frames(g, frames)
         if bins == base:
-            default_ms = _time_frames(g, frames)
+            default_ms = ms0
         plan, best, start = g.autotune(reps)
         ms = _time_frames(g, frames)
+        if ms >= ms0:
+            plan, ms = plan0, ms0
         g.close()
         results.append({"bins": bins, "plan": plan, "frame_ms": ms, "splat_ms": best, "splat_ms_start": start})
         log(f"[autotune] bins {bins}: plan {plan}, {ms:.4f} ms/frame")

@@ -19,11 +19,12 @@
 // the estimates and the plan in one block for small scenes).  k_splat is a
 // grid over the
 // items: an item is one part of one tile.  Each bucket's list of particles
-// that can reach the tile is cut into blocks of kSplit consecutive entries
-// (one 128-byte line of 16-byte records) and part j of `nparts` takes blocks
-// j, j + nparts, ...: every part samples the whole tile, so its four
-// quadrants get about equal work (contiguous shares gave each part a band of
-// bin rows), while a record line is still read by one part only.  That list
+// that can reach the tile is dealt to its parts by record line: the
+// particle buffer is cut into aligned blocks of kSplit records (one 128-byte
+// line of 16-byte records) and part j of `nparts` takes the entries in blocks
+// whose index is j modulo nparts.  Every part samples the whole tile, so its
+// four quadrants get about equal work (contiguous shares gave each part a
+// band of bin rows), and every record line is fetched by one part only.  That list
 // is the bins whose crests lie within 2 r_b of the tile, contiguous runs of
 // the bin-sorted particle buffer.  The item decodes 256 particles at a time into
 // LDS (crest and trough centres in tile cells, signed amplitudes) and then
@@ -341,7 +342,18 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int
 
 // ---------------------------------------------------------------- splat
 constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
-constexpr int kSplit = 8;          // entries per block when a tile's lists are dealt to its parts
+constexpr int kSplit = 8;          // records per aligned block when a tile's lists are dealt to its parts
+
+// Entries of part j of np among the record indices [0, x): those in the
+// aligned kSplit-blocks whose block index is j modulo np.
+__device__ __forceinline__ int part_count(int x, int j, int np) {
+  const int span = kSplit * np;
+  return x / span * kSplit + min(kSplit, max(0, x % span - kSplit * j));
+}
+// Record index of the k-th entry (from 0) of part j of np; inverse of part_count.
+__device__ __forceinline__ int part_entry(int k, int j, int np) {
+  return k / kSplit * (kSplit * np) + kSplit * j + k % kSplit;
+}
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -521,7 +533,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
                                                     int ndirect, float *__restrict__ raw_out,
                                                     float *__restrict__ blend_out, int64_t out_off) {
   __shared__ __align__(16) float acc[kTile][kPad];
-  // per bucket: bin rows reaching the tile (start, exclusive prefix of lengths)
+  // per bucket: bin rows reaching the tile (this part's entries before the
+  // row's first record, exclusive prefix of this part's entries in the rows)
   __shared__ int s_rlo[kMaxBuckets][kMaxRows];
   __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
   __shared__ int s_nrows[kMaxBuckets];
@@ -578,8 +591,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
         nrows = rc4.w;
         if (r < nrows) {
           const int rb = P.binbase[b] + (rc4.z + r) * P.nbx[b];
-          lo = min(d.off[rb + rc4.x], d.cap);
-          len = max(0, min(d.off[rb + rc4.y + 1], d.cap) - lo);
+          const int a = min(d.off[rb + rc4.x], d.cap);
+          const int e = max(a, min(d.off[rb + rc4.y + 1], d.cap));
+          lo = part_count(a, part, nparts);
+          len = part_count(e, part, nparts) - lo;
         }
       }
       if (r < nrows) {
@@ -607,11 +622,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
       int cnt = 0;
       if (lane < nb) {
         const int b = nb - 1 - lane;
-        const int M = s_pre[b][s_nrows[b]];
-        // blocks part, part + nparts, ... of kSplit entries; the last block may be short
-        const int nblk = (M + kSplit - 1) / kSplit;
-        cnt = nblk > part ? (nblk - part + nparts - 1) / nparts * kSplit : 0;
-        if (nblk > 0 && (nblk - 1) % nparts == part) cnt -= nblk * kSplit - M;
+        cnt = s_pre[b][s_nrows[b]];   // this part's entries in the bucket's list
         s_cnt[b] = cnt;
       }
       const int nbj = (cnt + kBatch - 1) / kBatch;
@@ -645,14 +656,13 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
     // the lane's record of a batch: list entry -> this part's block -> bin row -> particle
     auto fetch = [&](int b, int e0, int cnt, Rec &rec) {
       if (lane < cnt) {
-        const int gl = e0 + lane;
-        const int v = (part + gl / kSplit * nparts) * kSplit + gl % kSplit;
+        const int v = e0 + lane;   // this part's v-th entry of the bucket's list
         int lo = 0, hi = s_nrows[b] - 1;   // last row with prefix <= v
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
           if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
         }
-        rec = S[s_rlo[b][lo] + (v - s_pre[b][lo])];
+        rec = S[part_entry(s_rlo[b][lo] + (v - s_pre[b][lo]), part, nparts)];
       }
     };
 
