@@ -138,6 +138,10 @@ typedef struct {
     int32_t chunk_load;     /* least estimated cost of one splat work item (model units) */
     int32_t items_target;   /* work items per frame the plan aims for beyond one per output tile */
     int32_t splat_grid;     /* persistent splat blocks launched; 0: four per compute unit */
+    int32_t splat_kernel;   /* splat schedule: 0 each wavefront splats its own batches of records
+                               (four quadrant accumulators per wavefront), 1 each wavefront owns one
+                               quadrant of the tile and the block decodes records into LDS; the
+                               same heights up to FP32 summation order */
 } hwo_plan;
 
 typedef struct {
@@ -343,15 +347,15 @@ int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep
 /* Tuning of the per-bucket splat (Sec 4.2: the per-bucket layers of Fig 1's
  * pairs, here one launch over all tiles of all patches).  hwo_get_plan
  * reports the current work partition; hwo_set_plan replaces it (chunk_load
- * 64..2^24, items_target 0..8192, splat_grid 0..65535; HWO_EINVAL
- * otherwise), effective from the next step (the frame graph is captured
- * again).  hwo_autotune searches the partition on the current frame: after
- * at least one step it re-runs the plan, splat and reduce stages (which
- * rewrite the same heights, up to FP32 summation order) reps times per
- * candidate, coordinate by coordinate over chunk_load, items_target and
- * splat_grid, keeps the fastest, sets it and reports it with its time and
- * that of the partition it started from (milliseconds per plan + splat +
- * reduce).  Integer state is never touched.  HWO_ESTATE before the first
+ * 64..2^24, items_target 0..8192, splat_grid 0..65535, splat_kernel 0 or 1;
+ * HWO_EINVAL otherwise), effective from the next step (the frame graph is
+ * captured again).  hwo_autotune searches the partition on the current
+ * frame: after at least one step it re-runs the plan, splat and reduce
+ * stages (which rewrite the same heights, up to FP32 summation order) reps
+ * times per candidate, for each splat schedule coordinate by coordinate over
+ * chunk_load, items_target and splat_grid, keeps the fastest, sets it and
+ * reports it with its time and that of the partition it started from
+ * (milliseconds per plan + splat + reduce).  Integer state is never touched.  HWO_ESTATE before the first
  * step, HWO_EINVAL with texel layers (synth 1) or reps < 1.  Synchronise. */
 int hwo_get_plan(hwo_ocean *o, hwo_plan *out);
 int hwo_set_plan(hwo_ocean *o, const hwo_plan *plan);

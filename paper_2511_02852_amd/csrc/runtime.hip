@@ -1602,13 +1602,14 @@ int hwo_get_plan(hwo_ocean *o, hwo_plan *out) {
   out->chunk_load = (int32_t)o->dev.chunk_load;
   out->items_target = o->items_target;
   out->splat_grid = o->splat_grid;
+  out->splat_kernel = o->dev.splat_kernel;
   return HWO_OK;
 }
 
 int hwo_set_plan(hwo_ocean *o, const hwo_plan *p) {
   if (!o || !p) return HWO_EINVAL;
   if (p->chunk_load < 64 || p->chunk_load > (1 << 24) || p->items_target < 0 || p->items_target > 8192 ||
-      p->splat_grid < 0 || p->splat_grid > 65535)
+      p->splat_grid < 0 || p->splat_grid > 65535 || (p->splat_kernel != 0 && p->splat_kernel != 1))
     return o->fail(HWO_EINVAL, "plan parameter out of range");
   int rc = finalize(o);
   if (rc) return rc;
@@ -1616,6 +1617,7 @@ int hwo_set_plan(hwo_ocean *o, const hwo_plan *p) {
   o->dev.chunk_load = (uint32_t)p->chunk_load;
   o->items_target = p->items_target;
   o->splat_grid = p->splat_grid;
+  o->dev.splat_kernel = p->splat_kernel;
   drop_graph(o);   // the plan parameters are kernel arguments of the captured frame
   return HWO_OK;
 }
@@ -1656,47 +1658,67 @@ int hwo_autotune(hwo_ocean *o, int32_t reps, hwo_plan *best, double *best_ms, do
   int rc = collect_timing(o);
   if (rc) return rc;
   Dev &d = o->dev;
-  hwo_plan cur{(int32_t)d.chunk_load, o->items_target, o->splat_grid};
+  const hwo_plan start{(int32_t)d.chunk_load, o->items_target, o->splat_grid, d.splat_kernel};
   auto apply = [&](const hwo_plan &p) {
     d.chunk_load = (uint32_t)p.chunk_load;
     o->items_target = p.items_target;
     o->splat_grid = p.splat_grid;
+    d.splat_kernel = p.splat_kernel;
   };
-  double t_cur = 0.0;
-  rc = time_partition(o, reps, &t_cur);
+  double t_start = 0.0;
+  rc = time_partition(o, reps, &t_start);
   if (rc) return rc;
-  *start_ms = t_cur;
+  *start_ms = t_start;
+  hwo_plan best_plan = start;
+  double t_best = t_start;
   const int room = std::min(8192, d.max_items - d.ntiles);
   const int tb = o->target_blocks;   // four per compute unit
   const std::vector<int32_t> chunks = {1000, 1750, 2500, 3500, 5000, 7000, 10000, 14000};
   const std::vector<int32_t> items = {256, 512, 1024, 2048, 4096, 8192};
   const std::vector<int32_t> grids = {tb / 2, tb, 2 * tb, 4 * tb, 8 * tb};
-  // two sweeps of coordinate descent
-  for (int sweep = 0; sweep < 2; ++sweep) {
-    for (int coord = 0; coord < 3; ++coord) {
-      const std::vector<int32_t> &vals = coord == 0 ? chunks : coord == 1 ? items : grids;
-      for (int32_t v : vals) {
-        hwo_plan p = cur;
-        if (coord == 0) p.chunk_load = v;
-        if (coord == 1) {
-          if (v > room) continue;
-          p.items_target = v;
+  // for each splat schedule, two sweeps of coordinate descent from the
+  // starting partition
+  for (int32_t kern = 0; kern < 2; ++kern) {
+    hwo_plan cur = start;
+    cur.splat_kernel = kern;
+    apply(cur);
+    double t_cur = t_start;
+    if (kern != start.splat_kernel) {
+      rc = time_partition(o, reps, &t_cur);
+      if (rc) return rc;
+    }
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      for (int coord = 0; coord < 3; ++coord) {
+        const std::vector<int32_t> &vals = coord == 0 ? chunks : coord == 1 ? items : grids;
+        for (int32_t v : vals) {
+          hwo_plan p = cur;
+          if (coord == 0) p.chunk_load = v;
+          if (coord == 1) {
+            if (v > room) continue;
+            p.items_target = v;
+          }
+          if (coord == 2) p.splat_grid = std::max(1, v);
+          if (p.chunk_load == cur.chunk_load && p.items_target == cur.items_target && p.splat_grid == cur.splat_grid)
+            continue;
+          apply(p);
+          double t = 0.0;
+          rc = time_partition(o, reps, &t);
+          if (rc) return rc;
+          if (t < t_cur) {
+            t_cur = t;
+            cur = p;
+          }
         }
-        if (coord == 2) p.splat_grid = std::max(1, v);
-        if (p.chunk_load == cur.chunk_load && p.items_target == cur.items_target && p.splat_grid == cur.splat_grid)
-          continue;
-        apply(p);
-        double t = 0.0;
-        rc = time_partition(o, reps, &t);
-        if (rc) return rc;
-        if (t < t_cur) {
-          t_cur = t;
-          cur = p;
-        }
+        apply(cur);
       }
-      apply(cur);
+    }
+    if (t_cur < t_best) {
+      t_best = t_cur;
+      best_plan = cur;
     }
   }
+  const hwo_plan cur = best_plan;
+  const double t_cur = t_best;
   apply(cur);
   drop_graph(o);
   // leave the frame's outputs from the chosen partition

@@ -24,19 +24,22 @@
 // line of 16-byte records) and part j of `nparts` takes the entries in blocks
 // whose index is j modulo nparts.  Every part samples the whole tile, so its
 // four quadrants get about equal work (contiguous shares gave each part a
-// band of bin rows), and every record line is fetched by one part only.  That list
-// is the bins whose crests lie within 2 r_b of the tile, contiguous runs of
-// the bin-sorted particle buffer.  The item decodes 256 particles at a time into
-// LDS (crest and trough centres in tile cells, signed amplitudes) and then
-// runs each bucket's run of points through one of two paths:
-//   * footprints of at most 7 cells per axis: one point per lane, weights in
-//     registers, A w(d_x) w(d_y) added to the LDS tile with LDS float atomics;
+// band of bin rows), and every record line is fetched by one part only.  That
+// list is the bins whose crests lie within 2 r_b of the tile, contiguous runs
+// of the bin-sorted particle buffer.  The wavefronts of the block take
+// batches of 64 list entries and work independently (the kernel's own
+// comment has the schedule): each lane decodes one record into a crest and
+// a trough point in tile cells, and the batch goes through one of two paths:
+//   * footprints of at most kAtomicSpan cells per axis: each lane adds its
+//     two points, weights in registers, A w(d_x) w(d_y) into the LDS tile
+//     with LDS float atomics;
 //   * larger footprints: the separable kernel makes the tile a sum of outer
-//     products, H += W_y^T (A W_x).  Each wavefront owns a 32x32 quadrant and
-//     feeds the points that reach it, two at a time, to a 32x32x2 FP32
-//     matrix-core product; every lane computes the one row weight and the
-//     one column weight it supplies.  The quadrant accumulators are added to
-//     the LDS tile at the end of the item.
+//     products, H += W_y^T (A W_x).  For each 32x32 quadrant some point of
+//     the batch reaches, the points are fed two at a time to a 32x32x2 FP32
+//     matrix-core product into the wavefront's accumulator of that quadrant;
+//     every lane computes the one row weight and the one column weight it
+//     supplies.  The four accumulators of every wavefront are added to the
+//     LDS tile at the end of the item.
 // A tile with one part is blended and written straight from LDS.  Parts of a
 // split tile store their partial tile; k_splat_reduce (the next launch, so
 // every store is visible on every XCD) sums them and runs the blend.
@@ -510,14 +513,15 @@ __device__ __forceinline__ int pop_point(uint64_t &m0, uint64_t &m1) {
 // both are template parameters so that the default instance carries neither.
 // Each work item (one part of one output tile) is processed as follows.  The
 // block loads the bin rows of every bucket that reach the tile and cuts each
-// bucket's list (this part's share) into batches of 64 entries.  Wavefronts
-// then take batches from a counter in LDS, largest buckets first, and work
-// independently: every lane loads and decodes one record (the next batch's
-// records are loaded while the current one is splatted) into a crest and a
-// trough point, and the batch goes through one of two paths into the LDS
+// bucket's list (this part's share) into batches of 64 entries, ordered from
+// the largest radii down.  Wavefront w takes batches w, w + 4, w + 8, ...
+// and works independently: every lane loads and decodes one record into a
+// crest and a trough point (three batches are in flight: the records of
+// batch k + 2 load while the table loads of batch k + 1 and the splat of
+// batch k run), and the batch goes through one of two paths into the LDS
 // tile:
-//   * footprints of at most 7 cells per axis: each lane adds its two points
-//     cell by cell with LDS float atomics, weights in registers;
+//   * footprints of at most kAtomicSpan cells per axis: each lane adds its
+//     two points cell by cell with LDS float atomics, weights in registers;
 //   * larger footprints: for each 32 x 32 quadrant of the tile that some of
 //     the batch's points reach, the points (read from their lanes'
 //     registers) are fed two at a time to a 32x32x2 FP32 matrix-core product
@@ -868,6 +872,304 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
   }
 }
 
+// ---------------------------------------------------------------- splat, quadrant-owner schedule
+// The second schedule of the same splat, for scenes whose footprints are
+// mostly large (long waves on fine patches): the block decodes its list 256
+// records at a time into LDS (a crest and a trough point per record, with
+// the quadrants each reaches), then splats that chunk bucket by bucket:
+//   * footprints of at most 7 cells per axis: the chunk's points are spread
+//     over all four wavefronts, one per lane, LDS float atomics;
+//   * larger footprints: wavefront w owns quadrant w of the tile and feeds
+//     the chunk's points that reach it, two at a time, to the 32x32x2 FP32
+//     matrix-core product into its one accumulator (the radial kernel
+//     accumulates the quadrant's cells point by point instead).
+// One accumulator per wavefront keeps the kernel at five wavefronts per
+// SIMD, which hides the latency of the per-pair weight and product chain;
+// the batch schedule above holds four accumulators per wavefront (three
+// wavefronts per SIMD) and wins where small footprints dominate.  Both give
+// the same heights up to FP32 summation order.
+constexpr int kChunk = kThreads;   // records decoded into LDS per round
+constexpr int kQuadAtomicSpan = 7;
+
+template <class Rec, bool kRadial, bool kProf>
+__global__ __launch_bounds__(kThreads, 5) void k_splat_q(Dev d, int t0, int nt, const Rec *__restrict__ direct,
+                                                      int ndirect, float *__restrict__ raw_out,
+                                                      float *__restrict__ blend_out, int64_t out_off) {
+  __shared__ __align__(16) float acc[kTile][kPad];
+  // decoded chunk: for record i of the chunk, pt[2i] is its crest and
+  // pt[2i + 1] its trough: centre (tile cells), signed amplitude (0: skip),
+  // quadrants reached (bit w: quadrant of wavefront w)
+  __shared__ float4 pt[2 * kChunk];
+  __shared__ int s_rlo[kMaxBuckets][kMaxRows];
+  __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
+  __shared__ int s_nrows[kMaxBuckets];
+  __shared__ int s_boff[kMaxBuckets + 1];    // offsets of the buckets in this part's list
+  __shared__ int s_tile, s_part, s_nparts, s_patch;
+  __shared__ unsigned long long s_prof[kProf ? PROF_N : 1];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  constexpr int nwaves = kThreads / 64;
+  const int64_t n = d.glob->n;
+  const Rec *__restrict__ S = direct ? direct : (const Rec *)((n & 1) ? d.S1 : d.S0);
+  const int total = direct ? nt : d.splat_ctl[1];
+  const int nb = d.nb;
+  // matrix-core path: wavefront w owns the 32 x 32 quadrant (xq, yq) of the tile
+  const int xq = 32 * (wave & 1), yq = 32 * (wave >> 1);
+  uint64_t t_mark = 0;
+  auto mark = [&](int cat) {
+    if constexpr (kProf) {
+      const uint64_t now = __builtin_amdgcn_s_memtime();
+      if (lane == 0) atomicAdd(&s_prof[cat], (unsigned long long)(now - t_mark));
+      t_mark = now;
+    }
+  };
+  if constexpr (kProf)
+    for (int i = tid; i < PROF_N; i += kThreads) s_prof[i] = 0ull;
+
+  for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
+    if constexpr (kProf) t_mark = __builtin_amdgcn_s_memtime();
+    if (tid == 0) {
+      const int4 e = direct ? make_int4(t0 + item, 0, 1, d.tile_patch[t0 + item]) : d.item_desc[item];
+      s_tile = e.x;
+      s_part = e.y;
+      s_nparts = e.z;
+      s_patch = e.w;
+    }
+    for (int c = tid; c < kTile * kPad / 4; c += kThreads)
+      reinterpret_cast<float4 *>(&acc[0][0])[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    const int tile = s_tile, part = s_part, nparts = s_nparts;
+    TileGeom T;
+    tile_geom(d, tile, s_patch, T);
+    const PatchDev &P = d.patches[T.p];
+    // ---- row tables of every bucket (this part's entries), as in k_splat
+    for (int q = tid; q < nb * kMaxRows; q += kThreads) {
+      const int b = q / kMaxRows, r = q % kMaxRows;
+      int nrows, lo = 0, len = 0;
+      if (direct) {
+        nrows = 1;
+        if (r == 0) len = ndirect;
+      } else {
+        const short4 rc4 = d.tile_rect[(size_t)tile * nb + b];
+        nrows = rc4.w;
+        if (r < nrows) {
+          const int rb = P.binbase[b] + (rc4.z + r) * P.nbx[b];
+          const int a = min(d.off[rb + rc4.x], d.cap);
+          const int e = max(a, min(d.off[rb + rc4.y + 1], d.cap));
+          lo = part_count(a, part, nparts);
+          len = part_count(e, part, nparts) - lo;
+        }
+      }
+      if (r < nrows) {
+        s_rlo[b][r] = lo;
+        s_pre[b][r] = len;
+      }
+      if (r == 0) s_nrows[b] = nrows;
+    }
+    __syncthreads();
+    for (int b = wave; b < nb; b += nwaves) {
+      const int nrows = s_nrows[b];
+      const int len = lane < nrows ? s_pre[b][lane] : 0;
+      int inc = len;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+      }
+      if (lane < nrows) s_pre[b][lane] = inc - len;
+      if (lane == 63) s_pre[b][nrows] = inc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // bucket offsets in the item's list (buckets in index order)
+      const int cnt = lane < nb ? s_pre[lane][s_nrows[lane]] : 0;
+      int inc = cnt;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+      }
+      if (lane < nb) s_boff[lane] = inc - cnt;
+      if (lane == nb - 1) s_boff[nb] = inc;
+    }
+    __syncthreads();
+    mark(PROF_SETUP);
+    const int Mi = s_boff[nb];
+    const bool quad_live = xq < T.tw && yq < T.th;
+    f32x16 cq;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) cq[r] = 0.f;
+    const uint64_t t_work = __builtin_amdgcn_s_memrealtime();   // 100 MHz
+
+    // the records of chunk c + 1 are loaded while chunk c is splatted
+    Rec rec;
+    int rec_b = -1;   // bucket of the prefetched record, -1: none
+    auto fetch = [&](int c) {
+      rec_b = -1;
+      if (tid < min(kChunk, Mi - c)) {
+        // item-list index -> bucket -> bin row -> particle
+        const int g = c + tid;
+        int b = 0;
+        while (b + 1 < nb && s_boff[b + 1] <= g) ++b;
+        const int v = g - s_boff[b];
+        int lo = 0, hi = s_nrows[b] - 1;   // last row with prefix <= v
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
+        }
+        rec = S[part_entry(s_rlo[b][lo] + (v - s_pre[b][lo]), part, nparts)];
+        rec_b = b;
+      }
+    };
+    fetch(0);
+    for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
+      const int m = min(kChunk, Mi - c);
+      // ---- decode the prefetched records into crest and trough points
+      if (rec_b >= 0) {
+        const int b = rec_b;
+        const DecIn in = dec_load<Rec>(d, rec, n, b, T.p, true);
+        float cx, cy, A;
+        dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A);
+        const float rc = d.bucket_r[b] / (float)P.dx;
+        const float rev = (float)in.code * (1.0f / (float)kNCode);
+        const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
+        auto quads = [&](float x, float y) {
+          if (A == 0.f) return 0u;
+          return (uint32_t)reaches(x, y, rc, 0, 0) | (uint32_t)reaches(x, y, rc, 32, 0) << 1 |
+                 (uint32_t)reaches(x, y, rc, 0, 32) << 2 | (uint32_t)reaches(x, y, rc, 32, 32) << 3;
+        };
+        pt[2 * tid] = make_float4(cx, cy, A, __uint_as_float(quads(cx, cy)));
+        pt[2 * tid + 1] = make_float4(tx, ty, -A, __uint_as_float(quads(tx, ty)));
+      }
+      __syncthreads();
+      if (c + kChunk < Mi) fetch(c + kChunk);
+      mark(PROF_DECODE);
+      // ---- the chunk holds runs of consecutive buckets
+      for (int b = 0; b < nb; ++b) {
+        const int seg_lo = max(c, s_boff[b]) - c, seg_hi = min(c + m, s_boff[b + 1]) - c;
+        if (seg_hi <= seg_lo) continue;   // block-uniform
+        if constexpr (kProf)
+          if (tid == 0) atomicAdd(&s_prof[PROF_POINTS + b], (unsigned long long)(2 * (seg_hi - seg_lo)));
+        const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
+        const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
+        const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
+        const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
+        if (span <= kQuadAtomicSpan) {
+          // ---- small footprints: points spread over all wavefronts
+          for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
+            const int q = q0 + lane;
+            const bool valid = q < q_hi;
+            const float4 pv = pt[valid ? q : q_lo];
+            if constexpr (kRadial) {
+              if (span <= 3) splat_points_radial<4>(acc, pv, valid, rc, qs, T.tw, T.th);
+              else splat_points_radial<8>(acc, pv, valid, rc, qs, T.tw, T.th);
+            } else {
+              if (span <= 3) splat_points<4>(acc, pv, valid, rc, qs, T.tw, T.th);
+              else splat_points<8>(acc, pv, valid, rc, qs, T.tw, T.th);
+            }
+          }
+        } else if (quad_live) {
+          if constexpr (kRadial) {
+            // no outer-product form: each lane accumulates the 16 cells it
+            // holds in the matrix-core layout (column xq + lane % 32, rows
+            // yq + 8 (r / 4) + 4 (lane / 32) + r % 4), point by point
+            const float dxl = (float)(xq + (lane & 31)), ybase = (float)(yq + 4 * (lane >> 5));
+            for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
+              const int q = q0 + lane;
+              const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
+              uint64_t mask = __ballot(hit);
+              while (mask) {   // wave-uniform
+                const float4 pv = pt[q0 + __builtin_ctzll(mask)];
+                mask &= mask - 1;
+                const float dx = dxl - pv.x, dx2 = dx * dx;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                  const float dy = ybase + (float)(8 * (r >> 2) + (r & 3)) - pv.y;
+                  cq[r] += pv.z * wrev(__builtin_amdgcn_sqrtf(dx2 + dy * dy) * qs);
+                }
+              }
+            }
+          } else {
+            // rank-2 update D += W_y(:, k1 k2) [A_k1 W_x(k1, :); A_k2 W_x(k2, :)]
+            // for each pair of the chunk's points that reach the quadrant
+            // (lanes 0-31 supply the first point, 32-63 the second)
+            const float yrow = (float)(yq + (lane & 31)), xcol = (float)(xq + (lane & 31));
+            for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
+              const int q = q0 + lane;
+              const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
+              uint64_t mask = __ballot(hit);
+              if (!mask) continue;   // wave-uniform
+              // the next pair's point is read from LDS before the current
+              // pair's product is issued
+              auto pop = [&](int &k1, int &k2, float &keep) {
+                k1 = __builtin_ctzll(mask);
+                mask &= mask - 1;
+                k2 = k1;
+                keep = lane < 32 ? 1.f : 0.f;   // odd count: the second copy gets no weight
+                if (mask) {
+                  k2 = __builtin_ctzll(mask);
+                  mask &= mask - 1;
+                  keep = 1.f;
+                }
+              };
+              int k1, k2;
+              float keep;
+              pop(k1, k2, keep);
+              float4 pv = pt[q0 + (lane < 32 ? k1 : k2)];
+              while (true) {
+                const bool more = mask != 0;   // wave-uniform
+                float4 pn = pv;
+                float keep_n = 0.f;
+                if (more) {
+                  pop(k1, k2, keep_n);
+                  pn = pt[q0 + (lane < 32 ? k1 : k2)];
+                }
+                const float a = wrev((yrow - pv.y) * qs);
+                const float bw = keep * pv.z * wrev((xcol - pv.x) * qs);
+                cq = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bw, cq, 0, 0, 0);
+                if (!more) break;
+                pv = pn;
+                keep = keep_n;
+              }
+            }
+          }
+        }
+        mark(PROF_BUCKET + b);
+      }
+      __syncthreads();
+      mark(PROF_WAIT);
+    }
+    // ---- the matrix-core quadrants into the tile (disjoint per wavefront)
+    if (quad_live) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = yq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        acc[row][xq + (lane & 31)] += cq[r];
+      }
+    }
+    __syncthreads();
+    // time spent on this item's particles, for the next frame's plan
+    if (tid == 0 && !direct)
+      atomicAdd(&d.tile_meas[tile], (uint32_t)min<uint64_t>(__builtin_amdgcn_s_memrealtime() - t_work, 0x3FFFFFFFull));
+    if (nparts == 1) {
+      const StepPatch &W = d.sp[T.p];
+      for (int c = tid; c < kTile * kTile; c += kThreads) {
+        const int i = c % kTile, j = c / kTile;
+        if (i < T.tw && j < T.th) blend_store(d, P, W, T, i, j, acc[j][i], raw_out, blend_out, out_off);
+      }
+    } else {
+      float *dst = d.partials + (size_t)item * (kTile * kTile);
+      for (int c = tid; c < kTile * kTile; c += kThreads) dst[c] = acc[c / kTile][c % kTile];
+    }
+    __syncthreads();
+    mark(PROF_EPILOGUE);
+  }
+  if constexpr (kProf) {
+    __syncthreads();
+    for (int i = tid; i < PROF_N; i += kThreads)
+      if (s_prof[i]) atomicAdd(&d.splat_prof[i], s_prof[i]);
+  }
+}
+
 // ---------------------------------------------------------------- reduce
 // Persistent grid over the units (split tile, stripe of 4 rows) listed by the
 // plan: sums the partial tiles of the split tile and runs the blend.  Tiles
@@ -944,12 +1246,20 @@ void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipS
 template <bool kRadial, bool kProf>
 void splat_launch(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,
                   int64_t out_off, hipStream_t st) {
-  if (d.compact)
+  if (d.splat_kernel == 1) {
+    if (d.compact)
+      hipLaunchKernelGGL((k_splat_q<RecCompact, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+                         (const RecCompact *)recs, n, raw, blend, out_off);
+    else
+      hipLaunchKernelGGL((k_splat_q<RecWide, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+                         (const RecWide *)recs, n, raw, blend, out_off);
+  } else if (d.compact) {
     hipLaunchKernelGGL((k_splat<RecCompact, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
                        (const RecCompact *)recs, n, raw, blend, out_off);
-  else
+  } else {
     hipLaunchKernelGGL((k_splat<RecWide, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
                        (const RecWide *)recs, n, raw, blend, out_off);
+  }
 }
 
 void splat_launch_any(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,

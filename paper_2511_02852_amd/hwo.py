@@ -52,7 +52,8 @@ class HwoPatch(C.Structure):
 
 
 class HwoPlan(C.Structure):
-    _fields_ = [("chunk_load", C.c_int32), ("items_target", C.c_int32), ("splat_grid", C.c_int32)]
+    _fields_ = [("chunk_load", C.c_int32), ("items_target", C.c_int32), ("splat_grid", C.c_int32),
+                ("splat_kernel", C.c_int32)]
 
 
 class HwoSource(C.Structure):
@@ -346,13 +347,15 @@ class Ocean:
                 "bucket": v[4:4 + nb].copy(), "points": v[20:20 + nb].copy()}
 
     def get_plan(self) -> dict:
-        """Current work partition of the splat (chunk_load, items_target, splat_grid)."""
+        """Current work partition of the splat (chunk_load, items_target,
+        splat_grid, splat_kernel)."""
         p = HwoPlan()
         self._check(self.L.hwo_get_plan(self.h, C.byref(p)))
-        return {"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid}
+        return {"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid,
+                "splat_kernel": p.splat_kernel}
 
-    def set_plan(self, chunk_load: int, items_target: int, splat_grid: int = 0):
-        p = HwoPlan(int(chunk_load), int(items_target), int(splat_grid))
+    def set_plan(self, chunk_load: int, items_target: int, splat_grid: int = 0, splat_kernel: int = 0):
+        p = HwoPlan(int(chunk_load), int(items_target), int(splat_grid), int(splat_kernel))
         self._check(self.L.hwo_set_plan(self.h, C.byref(p)))
 
     def autotune(self, reps: int = 5):
@@ -361,7 +364,8 @@ class Ocean:
         p = HwoPlan()
         best, start = C.c_double(), C.c_double()
         self._check(self.L.hwo_autotune(self.h, int(reps), C.byref(p), C.byref(best), C.byref(start)))
-        return ({"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid},
+        return ({"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid,
+                 "splat_kernel": p.splat_kernel},
                 float(best.value), float(start.value))
 
     def time_stage(self, stage: str, reps: int = 20) -> float:

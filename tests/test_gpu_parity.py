@@ -325,15 +325,25 @@ def test_gpu_pair_lattice_cosine(compact):
     assert err <= 2e-5 * A, err
 
 
-@pytest.mark.parametrize("compact", [False, True])
-def test_gpu_splat_random_particles(compact):
-    """Hand-placed boundary and ring particles of every bucket, c2 geometry."""
+def use_schedule(g, splat_kernel):
+    """Select the splat schedule (0 batches per wavefront, 1 a quadrant per
+    wavefront) on a built ocean."""
+    p = g.get_plan()
+    p["splat_kernel"] = splat_kernel
+    g.set_plan(**p)
+
+
+@pytest.mark.parametrize("compact,splat_kernel", [(False, 0), (True, 0), (True, 1)])
+def test_gpu_splat_random_particles(compact, splat_kernel):
+    """Hand-placed boundary and ring particles of every bucket, c2 geometry,
+    through both splat schedules."""
     from paper_2511_02852_amd import hwo
     s = scenes.c2()
     g = hwo.Ocean(s, compact=compact)
     o = oracle.Oracle(s)
     g.step(1)
     o.step(1)
+    use_schedule(g, splat_kernel)
     wx, wy = o.window(0)
     rng = np.random.default_rng(4)
     dxu = int(0.25 * 2 ** 20)
@@ -392,17 +402,19 @@ def test_gpu_texel_layers_random_particles(compact):
     assert e <= 1e-5
 
 
-@pytest.mark.parametrize("compact", [False, True])
-def test_gpu_radial_kernel_random_particles(compact):
+@pytest.mark.parametrize("compact,splat_kernel", [(False, 0), (True, 0), (True, 1)])
+def test_gpu_radial_kernel_random_particles(compact, splat_kernel):
     """The radial kernel W(|d|) through the test hook: hand-placed boundary
     and ring particles of every bucket (small footprints one point per lane,
-    large ones one point per wavefront), c2 geometry, against the oracle."""
+    large ones one point per wavefront), c2 geometry, against the oracle,
+    through both splat schedules."""
     from paper_2511_02852_amd import hwo
     s = scenes.c2().replace(kernel=1)
     g = hwo.Ocean(s, compact=compact)
     o = oracle.Oracle(s)
     g.step(1)
     o.step(1)
+    use_schedule(g, splat_kernel)
     wx, wy = o.window(0)
     rng = np.random.default_rng(6)
     dxu = int(0.25 * 2 ** 20)
@@ -424,6 +436,23 @@ def test_gpu_radial_kernel_random_particles(compact):
     e = rel_rms(h, ref)
     say(f"radial random rel rms {e:.2e}")
     assert e <= 1e-5
+
+
+@pytest.mark.parametrize("name,steps,kernel", [("c2", 60, 0), ("p0", 40, 0), ("c3", 12, 0), ("c2", 60, 1),
+                                               ("p0", 40, 1)])
+def test_quadrant_schedule_scenes(name, steps, kernel):
+    """The quadrant-per-wavefront splat schedule in the batched form (both
+    crest/trough kernels): integer state bit-exact and heights against the
+    oracle, as for the default schedule."""
+    s = scenes.get(name).replace(kernel=kernel)
+    say(f"quadrant schedule {name} kernel={kernel} {steps} steps")
+    g, o = make(s, compact=True, batched=True)
+    use_schedule(g, 1)
+    g.step(steps)
+    o.step(steps)
+    check_integer_state(g, o, s)
+    e = check_heights(g, o, s, patches=[0, 1, len(s.patches) - 1] if len(s.patches) > 3 else None)
+    say(f"quadrant schedule {name} kernel={kernel} err={e}")
 
 
 @pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "batched"),
