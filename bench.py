@@ -132,7 +132,7 @@ DOM_KERNEL = {"splat": "k_splat<RecCompact, false, false>", "fft_a": "k_fft_a", 
               "deposit_x": "k_deposit_x<RecCompact>", "filter_y": "k_filter_y", "layer_sum": "k_layer_sum"}
 
 
-def measured_traffic(config, dom, radial=False):
+def measured_traffic(config, dom, radial=False, splat_kernel=0):
     """HBM bytes per launch of the dominant kernel from profiles/traffic.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
     reads for a device copy of known size), or None when there is no entry
@@ -143,8 +143,9 @@ def measured_traffic(config, dom, radial=False):
         return None
     e = json.load(open(path)).get(config)
     name = DOM_KERNEL.get(dom)
-    if radial and dom == "splat":
-        name = "k_splat<RecCompact, true, false>"
+    if dom == "splat":   # the schedule and the crest/trough kernel are template instances
+        name = ("k_splat_q" if splat_kernel == 1 else "k_splat") + \
+            ("<RecCompact, true, false>" if radial else "<RecCompact, false, false>")
     if not e or e.get("kernel") != name:
         return None
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in e["sources"])).hexdigest()
@@ -316,12 +317,17 @@ def trends(K, W, synth=0):
         pre = int(math.ceil(size / (c_min * sc.dt))) + 60
         g = hwo.Ocean(sc, compact=True, batched=True)
         spin(g, pre)
+        plan = None
+        if synth == 0:
+            # the library's own search of the splat partition and schedule
+            # on the steady-state frame (the bin edges stay as chosen above)
+            plan = g.autotune(4)[0]
         spin(g, W)
         ms = time_frames(g, K)
         live = live_total(g, sc)
         g.close()
         rows.append({"U10": u10, "n_omega": ns, "n_theta": ns, "ms_per_frame": round(ms, 5),
-                     "live_particles": live, "preroll_frames": pre})
+                     "live_particles": live, "preroll_frames": pre, "plan": plan})
         log(f"[trends] U10={u10} N={ns}: {ms:.4f} ms/frame, {live} live particles")
     torch.cuda.synchronize()
     return rows
@@ -488,7 +494,7 @@ def main():
     t_hbm = alg[dom] / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops_dom / (FP32_PEAK_TFLOPS * 1e12)
     traffic = measured_traffic(args.config + ("-layers" if layers else "") + ("-radial" if radial else ""), dom,
-                               radial)
+                               radial, tuned["plan"].get("splat_kernel", 0) if tuned else 0)
     if (layers or radial) and t_mfma > t_hbm:
         # the layer passes and the radial kernel are FP32 vector work (no
         # matrix cores): bound by the vector ALUs, FP32 vector peak 157.3 TFLOP/s

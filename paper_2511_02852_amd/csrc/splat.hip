@@ -877,8 +877,8 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
 // mostly large (long waves on fine patches): the block decodes its list 256
 // records at a time into LDS (a crest and a trough point per record, with
 // the quadrants each reaches), then splats that chunk bucket by bucket:
-//   * footprints of at most 7 cells per axis: the chunk's points are spread
-//     over all four wavefronts, one per lane, LDS float atomics;
+//   * small footprints (kQuadAtomicSpan cells per axis): the chunk's points
+//     are spread over all four wavefronts, one per lane, LDS float atomics;
 //   * larger footprints: wavefront w owns quadrant w of the tile and feeds
 //     the chunk's points that reach it, two at a time, to the 32x32x2 FP32
 //     matrix-core product into its one accumulator (the radial kernel
@@ -889,7 +889,10 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
 // wavefronts per SIMD) and wins where small footprints dominate.  Both give
 // the same heights up to FP32 summation order.
 constexpr int kChunk = kThreads;   // records decoded into LDS per round
-constexpr int kQuadAtomicSpan = 7;
+// Footprints of at most this many cells per axis go through LDS atomics
+// (measured: 4 for the separable kernel, whose matrix-core products are
+// cheap; 7 for the radial one, whose quadrant path evaluates every cell).
+constexpr int kQuadAtomicSpan = 4, kQuadAtomicSpanRadial = 7;
 
 template <class Rec, bool kRadial, bool kProf>
 __global__ __launch_bounds__(kThreads, 5) void k_splat_q(Dev d, int t0, int nt, const Rec *__restrict__ direct,
@@ -1053,7 +1056,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_q(Dev d, int t0, int nt, 
         const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
         const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
         const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
-        if (span <= kQuadAtomicSpan) {
+        if (span <= (kRadial ? kQuadAtomicSpanRadial : kQuadAtomicSpan)) {
           // ---- small footprints: points spread over all wavefronts
           for (int q0 = q_lo + 64 * wave; q0 < q_hi; q0 += 64 * nwaves) {
             const int q = q0 + lane;
