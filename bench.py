@@ -132,7 +132,7 @@ DOM_KERNEL = {"splat": "k_splat<RecCompact, false, false>", "fft_a": "k_fft_a", 
               "deposit_x": "k_deposit_x<RecCompact>", "filter_y": "k_filter_y", "layer_sum": "k_layer_sum"}
 
 
-def measured_traffic(config, dom, radial=False, splat_kernel=0):
+def measured_traffic(config, dom, radial=False, splat_kernel=2):
     """HBM bytes per launch of the dominant kernel from profiles/traffic.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
     reads for a device copy of known size), or None when there is no entry
@@ -144,7 +144,7 @@ def measured_traffic(config, dom, radial=False, splat_kernel=0):
     e = json.load(open(path)).get(config)
     name = DOM_KERNEL.get(dom)
     if dom == "splat":   # the schedule and the crest/trough kernel are template instances
-        name = ("k_splat_q" if splat_kernel == 1 else "k_splat") + \
+        name = ("k_splat", "k_splat_q", "k_splat_h")[splat_kernel] + \
             ("<RecCompact, true, false>" if radial else "<RecCompact, false, false>")
     if not e or e.get("kernel") != name:
         return None
@@ -494,7 +494,7 @@ def main():
     t_hbm = alg[dom] / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops_dom / (FP32_PEAK_TFLOPS * 1e12)
     traffic = measured_traffic(args.config + ("-layers" if layers else "") + ("-radial" if radial else ""), dom,
-                               radial, tuned["plan"].get("splat_kernel", 0) if tuned else 0)
+                               radial, tuned["plan"].get("splat_kernel", 2) if tuned else 2)
     if (layers or radial) and t_mfma > t_hbm:
         # the layer passes and the radial kernel are FP32 vector work (no
         # matrix cores): bound by the vector ALUs, FP32 vector peak 157.3 TFLOP/s

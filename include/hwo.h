@@ -140,8 +140,9 @@ typedef struct {
     int32_t splat_grid;     /* persistent splat blocks launched; 0: four per compute unit */
     int32_t splat_kernel;   /* splat schedule: 0 each wavefront splats its own batches of records
                                (four quadrant accumulators per wavefront), 1 each wavefront owns one
-                               quadrant of the tile and the block decodes records into LDS; the
-                               same heights up to FP32 summation order */
+                               quadrant of the tile and the block decodes records into LDS, 2 the
+                               first for small footprints and then the second for large ones
+                               (default); the same heights up to FP32 summation order */
 } hwo_plan;
 
 typedef struct {
@@ -347,7 +348,7 @@ int hwo_time_stage(hwo_ocean *o, int32_t stage, int32_t reps, double *ms_per_rep
 /* Tuning of the per-bucket splat (Sec 4.2: the per-bucket layers of Fig 1's
  * pairs, here one launch over all tiles of all patches).  hwo_get_plan
  * reports the current work partition; hwo_set_plan replaces it (chunk_load
- * 64..2^24, items_target 0..8192, splat_grid 0..65535, splat_kernel 0 or 1;
+ * 64..2^24, items_target 0..8192, splat_grid 0..65535, splat_kernel 0..2;
  * HWO_EINVAL otherwise), effective from the next step (the frame graph is
  * captured again).  hwo_autotune searches the partition on the current
  * frame: after at least one step it re-runs the plan, splat and reduce

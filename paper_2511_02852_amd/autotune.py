@@ -7,9 +7,10 @@ Two kinds of parameters decide how the per-bucket splat is cut into work:
   reach of its footprints, so the edge trades sort granularity against the
   particles a tile reads without using them;
 * the work partition of the batched splat (least cost of a work item, item
-  budget per frame, persistent grid size) and which of its two schedules
-  runs (batches per wavefront or a quadrant per wavefront), searched on a
-  finished frame by the library itself (``hwo_autotune``).
+  budget per frame, persistent grid size) and which of its three schedules
+  runs (batches per wavefront, a quadrant per wavefront, or the hybrid of
+  the two), searched on a finished frame by the library itself
+  (``hwo_autotune``).
 
 ``tune`` builds one ocean per candidate set of bin edges, runs it to the
 pre-roll frame, lets the library tune the partition, times whole frames,
@@ -167,4 +168,4 @@ def tune(scene, preroll: int, cache: Optional[str] = None, reps: int = 8, frames
 def apply(ocean, tuned: dict):
     """Set the tuned splat partition on an ocean built with tuned["bins"]."""
     p = tuned["plan"]
-    ocean.set_plan(p["chunk_load"], p["items_target"], p["splat_grid"], p.get("splat_kernel", 0))
+    ocean.set_plan(p["chunk_load"], p["items_target"], p["splat_grid"], p.get("splat_kernel", 2))

@@ -188,7 +188,7 @@ struct Dev {
   const float2 *tw;            // [N] e^{2 pi i k / N}
   int32_t nfields;             // background fields: 1 height, or 5 (+ dH/dx, dH/dy, choppy Dx, Dy)
   int32_t fft_mfma16;          // 1: first FFT stage as a radix-16 DFT on the matrix cores (split bf16)
-  int32_t splat_kernel;        // splat schedule: 0 batches per wavefront, 1 quadrant per wavefront
+  int32_t splat_kernel;        // splat schedule: 0 batches per wavefront, 1 quadrant per wavefront, 2 both in turn
   float2 *FT;                  // [nfields][N/2+1][N]
   float *H;                    // [nfields][N][N], field 0 the height
   float *raw, *blend;          // heights, all patches

@@ -768,6 +768,7 @@ static int finalize(hwo_ocean *o) {
   // splat work plan
   d.max_items = d.ntiles + 8192;
   d.chunk_load = 3500;   // least estimated cost per work item (several hundred particle visits)
+  d.splat_kernel = 2;    // hybrid schedule: batches for small footprints, quadrants for large ones
   // Items beyond one per tile: about 16 parts per tile on average, between
   // 1024 and 4096.  Every extra part writes a 16 KiB partial tile that the
   // reduce reads back, so scenes with few dense tiles do better with fewer,
@@ -1609,7 +1610,7 @@ int hwo_get_plan(hwo_ocean *o, hwo_plan *out) {
 int hwo_set_plan(hwo_ocean *o, const hwo_plan *p) {
   if (!o || !p) return HWO_EINVAL;
   if (p->chunk_load < 64 || p->chunk_load > (1 << 24) || p->items_target < 0 || p->items_target > 8192 ||
-      p->splat_grid < 0 || p->splat_grid > 65535 || (p->splat_kernel != 0 && p->splat_kernel != 1))
+      p->splat_grid < 0 || p->splat_grid > 65535 || p->splat_kernel < 0 || p->splat_kernel > 2)
     return o->fail(HWO_EINVAL, "plan parameter out of range");
   int rc = finalize(o);
   if (rc) return rc;
@@ -1678,7 +1679,7 @@ int hwo_autotune(hwo_ocean *o, int32_t reps, hwo_plan *best, double *best_ms, do
   const std::vector<int32_t> grids = {tb / 2, tb, 2 * tb, 4 * tb, 8 * tb};
   // for each splat schedule, two sweeps of coordinate descent from the
   // starting partition
-  for (int32_t kern = 0; kern < 2; ++kern) {
+  for (int32_t kern = 0; kern < 3; ++kern) {
     hwo_plan cur = start;
     cur.splat_kernel = kern;
     apply(cur);

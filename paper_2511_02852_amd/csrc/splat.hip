@@ -1173,6 +1173,373 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_q(Dev d, int t0, int nt, 
   }
 }
 
+// ---------------------------------------------------------------- splat, hybrid schedule
+// The third schedule: each item runs the two schedules above one after the
+// other, each on the buckets it handles best.
+//   1. Buckets with footprints of at most kAtomicSpan cells per axis (7 with
+//      the radial kernel), as in k_splat: wavefronts take batches of 64
+//      entries independently (three batches in flight, no barrier), LDS
+//      float atomics.
+//   2. The other buckets, as in k_splat_q: the block decodes 256 records at
+//      a time into LDS and wavefront w feeds the points that reach quadrant w
+//      to the matrix cores, into its one accumulator.
+// Without the four accumulators of the batch schedule the kernel fits five
+// wavefronts per SIMD (at 96 registers a few of phase 1's values spill to
+// scratch, which measured faster than four wavefronts without spills: c5
+// 1.04 vs 1.08 ms, p0 0.16 vs 0.26 ms).  It is the default schedule.
+template <class Rec, bool kRadial, bool kProf>
+__global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, const Rec *__restrict__ direct,
+                                                      int ndirect, float *__restrict__ raw_out,
+                                                      float *__restrict__ blend_out, int64_t out_off) {
+  __shared__ __align__(16) float acc[kTile][kPad];
+  __shared__ float4 pt[2 * kChunk];           // phase 2: decoded chunk, as in k_splat_q
+  __shared__ int s_rlo[kMaxBuckets][kMaxRows];
+  __shared__ int s_pre[kMaxBuckets][kMaxRows + 1];
+  __shared__ int s_nrows[kMaxBuckets];
+  __shared__ int s_cnt[kMaxBuckets];          // entries of this part in each bucket's list
+  __shared__ int s_bat[kMaxBuckets + 1];      // phase 1: first batch of the j-th bucket taken (bucket nb - 1 - j)
+  __shared__ int s_boff[kMaxBuckets + 1];     // phase 2: offsets of the large buckets in the item's list
+  __shared__ int s_tile, s_part, s_nparts, s_patch;
+  __shared__ unsigned long long s_prof[kProf ? PROF_N : 1];
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  constexpr int nwaves = kThreads / 64;
+  const int64_t n = d.glob->n;
+  const Rec *__restrict__ S = direct ? direct : (const Rec *)((n & 1) ? d.S1 : d.S0);
+  const int total = direct ? nt : d.splat_ctl[1];
+  const int nb = d.nb;
+  const int xq = 32 * (wave & 1), yq = 32 * (wave >> 1);   // phase 2: the wavefront's quadrant
+  // footprints of at most this many cells per axis go through phase 1
+  constexpr int kSmall = kRadial ? kQuadAtomicSpanRadial : kAtomicSpan;
+  uint64_t t_mark = 0;
+  auto mark = [&](int cat) {
+    if constexpr (kProf) {
+      const uint64_t now = __builtin_amdgcn_s_memtime();
+      if (lane == 0) atomicAdd(&s_prof[cat], (unsigned long long)(now - t_mark));
+      t_mark = now;
+    }
+  };
+  if constexpr (kProf)
+    for (int i = tid; i < PROF_N; i += kThreads) s_prof[i] = 0ull;
+
+  for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
+    if constexpr (kProf) t_mark = __builtin_amdgcn_s_memtime();
+    if (tid == 0) {
+      const int4 e = direct ? make_int4(t0 + item, 0, 1, d.tile_patch[t0 + item]) : d.item_desc[item];
+      s_tile = e.x;
+      s_part = e.y;
+      s_nparts = e.z;
+      s_patch = e.w;
+    }
+    for (int c = tid; c < kTile * kPad / 4; c += kThreads)
+      reinterpret_cast<float4 *>(&acc[0][0])[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    const int tile = s_tile, part = s_part, nparts = s_nparts;
+    TileGeom T;
+    tile_geom(d, tile, s_patch, T);
+    const PatchDev &P = d.patches[T.p];
+    // ---- row tables of every bucket (this part's entries), as in k_splat
+    for (int q = tid; q < nb * kMaxRows; q += kThreads) {
+      const int b = q / kMaxRows, r = q % kMaxRows;
+      int nrows, lo = 0, len = 0;
+      if (direct) {
+        nrows = 1;
+        if (r == 0) len = ndirect;
+      } else {
+        const short4 rc4 = d.tile_rect[(size_t)tile * nb + b];
+        nrows = rc4.w;
+        if (r < nrows) {
+          const int rb = P.binbase[b] + (rc4.z + r) * P.nbx[b];
+          const int a = min(d.off[rb + rc4.x], d.cap);
+          const int e = max(a, min(d.off[rb + rc4.y + 1], d.cap));
+          lo = part_count(a, part, nparts);
+          len = part_count(e, part, nparts) - lo;
+        }
+      }
+      if (r < nrows) {
+        s_rlo[b][r] = lo;
+        s_pre[b][r] = len;
+      }
+      if (r == 0) s_nrows[b] = nrows;
+    }
+    __syncthreads();
+    for (int b = wave; b < nb; b += nwaves) {
+      const int nrows = s_nrows[b];
+      const int len = lane < nrows ? s_pre[b][lane] : 0;
+      int inc = len;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+      }
+      if (lane < nrows) s_pre[b][lane] = inc - len;
+      if (lane == 63) s_pre[b][nrows] = inc;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // lane j: the j-th bucket in phase-1 order (largest radii first) and
+      // bucket j for the phase-2 offsets
+      int cnt1 = 0, cnt2 = 0;
+      if (lane < nb) {
+        const int b = nb - 1 - lane;
+        const int span = (int)floorf(2.f * d.bucket_r[b] / (float)P.dx) + 1;
+        const int cnt = s_pre[b][s_nrows[b]];
+        cnt1 = span <= kSmall ? cnt : 0;
+        s_cnt[b] = cnt;
+        const int span2 = (int)floorf(2.f * d.bucket_r[lane] / (float)P.dx) + 1;
+        cnt2 = span2 <= kSmall ? 0 : s_pre[lane][s_nrows[lane]];
+      }
+      const int nbj = (cnt1 + kBatch - 1) / kBatch;
+      int inc = nbj, inc2 = cnt2;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(inc, o), y2 = __shfl_up(inc2, o);
+        if (lane >= o) {
+          inc += y;
+          inc2 += y2;
+        }
+      }
+      if (lane < nb) {
+        s_bat[lane] = inc - nbj;
+        s_boff[lane] = inc2 - cnt2;
+      }
+      if (lane == nb - 1) {
+        s_bat[nb] = inc;
+        s_boff[nb] = inc2;
+      }
+    }
+    __syncthreads();
+    mark(PROF_SETUP);
+    const uint64_t t_work = __builtin_amdgcn_s_memrealtime();   // 100 MHz
+
+    // ======== phase 1: small footprints, batches per wavefront
+    {
+      const int bat_lo = lane < nb ? s_bat[lane] : 0x7FFFFFFF;
+      const int bat_cnt = lane < nb ? s_cnt[nb - 1 - lane] : 0;
+      const int nbat = s_bat[nb];
+      auto locate = [&](int k, int &b, int &cnt) {
+        const int j = __popcll(__ballot(bat_lo <= k)) - 1;
+        b = nb - 1 - j;
+        const int e0 = (k - __builtin_amdgcn_readlane(bat_lo, j)) * kBatch;
+        cnt = min(kBatch, __builtin_amdgcn_readlane(bat_cnt, j) - e0);
+        return e0;
+      };
+      auto fetch = [&](int b, int e0, int cnt, Rec &rec) {
+        if (lane < cnt) {
+          const int v = e0 + lane;
+          int lo = 0, hi = s_nrows[b] - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
+          }
+          rec = S[part_entry(s_rlo[b][lo] + (v - s_pre[b][lo]), part, nparts)];
+        }
+      };
+      constexpr int kWaves = kThreads / 64;
+      int k0 = wave, b0 = 0, c0 = 0;
+      Rec r0, r1;
+      if (k0 < nbat) {
+        const int e0 = locate(k0, b0, c0);
+        fetch(b0, e0, c0, r0);
+      }
+      int k1 = wave + kWaves, b1 = 0, c1 = 0;
+      if (k1 < nbat) {
+        const int e0 = locate(k1, b1, c1);
+        fetch(b1, e0, c1, r1);
+      }
+      DecIn in0 = dec_load<Rec>(d, r0, n, b0, T.p, k0 < nbat && lane < c0);
+      while (k0 < nbat) {   // wave-uniform
+        const int k2 = k1 + kWaves;
+        int b2 = 0, c2 = 0;
+        Rec r2;
+        if (k2 < nbat) {
+          const int e0 = locate(k2, b2, c2);
+          fetch(b2, e0, c2, r2);
+        }
+        const int b = b0;
+        float cx, cy, A;
+        dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A);
+        const float rc = d.bucket_r[b] / (float)P.dx;
+        const float qs = 0.25f / rc;
+        const float rev = (float)in0.code * (1.0f / (float)kNCode);
+        const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
+        const DecIn in1 = dec_load<Rec>(d, r1, n, b1, T.p, k1 < nbat && lane < c1);
+        if constexpr (kProf)
+          if (lane == 0) atomicAdd(&s_prof[PROF_POINTS + b], (unsigned long long)(2 * c0));
+        mark(PROF_DECODE);
+        const float4 pc = make_float4(cx, cy, A, 0.f), ptr = make_float4(tx, ty, -A, 0.f);
+        const bool live = A != 0.f;
+        if constexpr (kRadial) {
+          if ((int)floorf(2.f * rc) + 1 <= 4) {   // wave-uniform
+            splat_points_radial<4>(acc, pc, live, rc, qs, T.tw, T.th);
+            splat_points_radial<4>(acc, ptr, live, rc, qs, T.tw, T.th);
+          } else {
+            splat_points_radial<8>(acc, pc, live, rc, qs, T.tw, T.th);
+            splat_points_radial<8>(acc, ptr, live, rc, qs, T.tw, T.th);
+          }
+        } else {
+          splat_points<kAtomicSpan>(acc, pc, live, rc, qs, T.tw, T.th);
+          splat_points<kAtomicSpan>(acc, ptr, live, rc, qs, T.tw, T.th);
+        }
+        mark(PROF_BUCKET + b);
+        k0 = k1; b0 = b1; c0 = c1;
+        k1 = k2; b1 = b2; c1 = c2;
+        r1 = r2;
+        in0 = in1;
+      }
+    }
+
+    // ======== phase 2: large footprints, one quadrant per wavefront
+    const int Mi = s_boff[nb];   // block-uniform
+    const bool quad_live = xq < T.tw && yq < T.th;
+    f32x16 cq;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) cq[r] = 0.f;
+    if (Mi > 0) {
+      Rec rec;
+      int rec_b = -1;
+      auto fetch2 = [&](int c) {
+        rec_b = -1;
+        if (tid < min(kChunk, Mi - c)) {
+          const int g = c + tid;
+          int b = 0;
+          while (b + 1 < nb && s_boff[b + 1] <= g) ++b;
+          const int v = g - s_boff[b];
+          int lo = 0, hi = s_nrows[b] - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[b][mid] <= v) lo = mid; else hi = mid - 1;
+          }
+          rec = S[part_entry(s_rlo[b][lo] + (v - s_pre[b][lo]), part, nparts)];
+          rec_b = b;
+        }
+      };
+      fetch2(0);
+      __syncthreads();   // phase 1 done everywhere before pt is written
+      mark(PROF_WAIT);
+      for (int c = 0; c < Mi; c += kChunk) {   // block-uniform
+        const int m = min(kChunk, Mi - c);
+        if (rec_b >= 0) {
+          const int b = rec_b;
+          const DecIn in = dec_load<Rec>(d, rec, n, b, T.p, true);
+          float cx, cy, A;
+          dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A);
+          const float rc = d.bucket_r[b] / (float)P.dx;
+          const float rev = (float)in.code * (1.0f / (float)kNCode);
+          const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
+          auto quads = [&](float x, float y) {
+            if (A == 0.f) return 0u;
+            return (uint32_t)reaches(x, y, rc, 0, 0) | (uint32_t)reaches(x, y, rc, 32, 0) << 1 |
+                   (uint32_t)reaches(x, y, rc, 0, 32) << 2 | (uint32_t)reaches(x, y, rc, 32, 32) << 3;
+          };
+          pt[2 * tid] = make_float4(cx, cy, A, __uint_as_float(quads(cx, cy)));
+          pt[2 * tid + 1] = make_float4(tx, ty, -A, __uint_as_float(quads(tx, ty)));
+        }
+        __syncthreads();
+        if (c + kChunk < Mi) fetch2(c + kChunk);
+        mark(PROF_DECODE);
+        for (int b = 0; b < nb; ++b) {
+          const int seg_lo = max(c, s_boff[b]) - c, seg_hi = min(c + m, s_boff[b + 1]) - c;
+          if (seg_hi <= seg_lo) continue;   // block-uniform
+          if constexpr (kProf)
+            if (tid == 0) atomicAdd(&s_prof[PROF_POINTS + b], (unsigned long long)(2 * (seg_hi - seg_lo)));
+          const float rc = d.bucket_r[b] / (float)P.dx;
+          const float qs = 0.25f / rc;
+          const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
+          if (quad_live) {
+            if constexpr (kRadial) {
+              const float dxl = (float)(xq + (lane & 31)), ybase = (float)(yq + 4 * (lane >> 5));
+              for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
+                const int q = q0 + lane;
+                const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
+                uint64_t mask = __ballot(hit);
+                while (mask) {   // wave-uniform
+                  const float4 pv = pt[q0 + __builtin_ctzll(mask)];
+                  mask &= mask - 1;
+                  const float dx = dxl - pv.x, dx2 = dx * dx;
+#pragma unroll
+                  for (int r = 0; r < 16; ++r) {
+                    const float dy = ybase + (float)(8 * (r >> 2) + (r & 3)) - pv.y;
+                    cq[r] += pv.z * wrev(__builtin_amdgcn_sqrtf(dx2 + dy * dy) * qs);
+                  }
+                }
+              }
+            } else {
+              const float yrow = (float)(yq + (lane & 31)), xcol = (float)(xq + (lane & 31));
+              for (int q0 = q_lo; q0 < q_hi; q0 += 64) {   // wave-uniform
+                const int q = q0 + lane;
+                const bool hit = q < q_hi && ((__float_as_uint(pt[q].w) >> wave) & 1u);
+                uint64_t mask = __ballot(hit);
+                if (!mask) continue;   // wave-uniform
+                auto pop = [&](int &k1, int &k2, float &keep) {
+                  k1 = __builtin_ctzll(mask);
+                  mask &= mask - 1;
+                  k2 = k1;
+                  keep = lane < 32 ? 1.f : 0.f;
+                  if (mask) {
+                    k2 = __builtin_ctzll(mask);
+                    mask &= mask - 1;
+                    keep = 1.f;
+                  }
+                };
+                int k1, k2;
+                float keep;
+                pop(k1, k2, keep);
+                float4 pv = pt[q0 + (lane < 32 ? k1 : k2)];
+                while (true) {
+                  const bool more = mask != 0;   // wave-uniform
+                  float4 pn = pv;
+                  float keep_n = 0.f;
+                  if (more) {
+                    pop(k1, k2, keep_n);
+                    pn = pt[q0 + (lane < 32 ? k1 : k2)];
+                  }
+                  const float a = wrev((yrow - pv.y) * qs);
+                  const float bw = keep * pv.z * wrev((xcol - pv.x) * qs);
+                  cq = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bw, cq, 0, 0, 0);
+                  if (!more) break;
+                  pv = pn;
+                  keep = keep_n;
+                }
+              }
+            }
+          }
+          mark(PROF_BUCKET + b);
+        }
+        __syncthreads();
+        mark(PROF_WAIT);
+      }
+    }
+    __syncthreads();   // phase 1 atomics (when phase 2 had nothing) before the quadrants are added
+    if (Mi > 0 && quad_live) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = yq + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        acc[row][xq + (lane & 31)] += cq[r];
+      }
+    }
+    __syncthreads();
+    if (tid == 0 && !direct)
+      atomicAdd(&d.tile_meas[tile], (uint32_t)min<uint64_t>(__builtin_amdgcn_s_memrealtime() - t_work, 0x3FFFFFFFull));
+    if (nparts == 1) {
+      const StepPatch &W = d.sp[T.p];
+      for (int c = tid; c < kTile * kTile; c += kThreads) {
+        const int i = c % kTile, j = c / kTile;
+        if (i < T.tw && j < T.th) blend_store(d, P, W, T, i, j, acc[j][i], raw_out, blend_out, out_off);
+      }
+    } else {
+      float *dst = d.partials + (size_t)item * (kTile * kTile);
+      for (int c = tid; c < kTile * kTile; c += kThreads) dst[c] = acc[c / kTile][c % kTile];
+    }
+    __syncthreads();
+    mark(PROF_EPILOGUE);
+  }
+  if constexpr (kProf) {
+    __syncthreads();
+    for (int i = tid; i < PROF_N; i += kThreads)
+      if (s_prof[i]) atomicAdd(&d.splat_prof[i], s_prof[i]);
+  }
+}
+
 // ---------------------------------------------------------------- reduce
 // Persistent grid over the units (split tile, stripe of 4 rows) listed by the
 // plan: sums the partial tiles of the split tile and runs the blend.  Tiles
@@ -1249,7 +1616,14 @@ void launch_bin_plan(const Dev &d, int nbins, int ntiles, int items_target, hipS
 template <bool kRadial, bool kProf>
 void splat_launch(const Dev &d, dim3 grid, int t0, int ntiles, const void *recs, int n, float *raw, float *blend,
                   int64_t out_off, hipStream_t st) {
-  if (d.splat_kernel == 1) {
+  if (d.splat_kernel == 2) {
+    if (d.compact)
+      hipLaunchKernelGGL((k_splat_h<RecCompact, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+                         (const RecCompact *)recs, n, raw, blend, out_off);
+    else
+      hipLaunchKernelGGL((k_splat_h<RecWide, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
+                         (const RecWide *)recs, n, raw, blend, out_off);
+  } else if (d.splat_kernel == 1) {
     if (d.compact)
       hipLaunchKernelGGL((k_splat_q<RecCompact, kRadial, kProf>), grid, dim3(kThreads), 0, st, d, t0, ntiles,
                          (const RecCompact *)recs, n, raw, blend, out_off);

@@ -354,7 +354,7 @@ class Ocean:
         return {"chunk_load": p.chunk_load, "items_target": p.items_target, "splat_grid": p.splat_grid,
                 "splat_kernel": p.splat_kernel}
 
-    def set_plan(self, chunk_load: int, items_target: int, splat_grid: int = 0, splat_kernel: int = 0):
+    def set_plan(self, chunk_load: int, items_target: int, splat_grid: int = 0, splat_kernel: int = 2):
         p = HwoPlan(int(chunk_load), int(items_target), int(splat_grid), int(splat_kernel))
         self._check(self.L.hwo_set_plan(self.h, C.byref(p)))
 

@@ -140,7 +140,7 @@ def test_call_order_errors(L):
     assert L.hwo_sample_probes_static(h, xy, 131073, out) == hwo.HWO_ERANGE   # beyond the static scratch
     assert L.hwo_sample_probes_static(h, xy, 2, out) == hwo.HWO_ESTATE        # nothing built, no step
     for bad in ((10, 100, 0, 0), (3500, -1, 0, 0), (3500, 9000, 0, 0), (3500, 100, -2, 0), (1 << 25, 0, 0, 0),
-                (3500, 100, 0, 2), (3500, 100, 0, -1)):
+                (3500, 100, 0, 3), (3500, 100, 0, -1)):
         assert L.hwo_set_plan(h, C.byref(hwo.HwoPlan(*bad))) == hwo.HWO_EINVAL, bad
     assert L.hwo_set_plan(h, None) == hwo.HWO_EINVAL
     plan, t1, t2 = hwo.HwoPlan(), C.c_double(), C.c_double()

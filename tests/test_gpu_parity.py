@@ -327,13 +327,13 @@ def test_gpu_pair_lattice_cosine(compact):
 
 def use_schedule(g, splat_kernel):
     """Select the splat schedule (0 batches per wavefront, 1 a quadrant per
-    wavefront) on a built ocean."""
+    wavefront, 2 the hybrid default) on a built ocean."""
     p = g.get_plan()
     p["splat_kernel"] = splat_kernel
     g.set_plan(**p)
 
 
-@pytest.mark.parametrize("compact,splat_kernel", [(False, 0), (True, 0), (True, 1)])
+@pytest.mark.parametrize("compact,splat_kernel", [(False, 2), (True, 0), (True, 1), (True, 2)])
 def test_gpu_splat_random_particles(compact, splat_kernel):
     """Hand-placed boundary and ring particles of every bucket, c2 geometry,
     through both splat schedules."""
@@ -402,7 +402,7 @@ def test_gpu_texel_layers_random_particles(compact):
     assert e <= 1e-5
 
 
-@pytest.mark.parametrize("compact,splat_kernel", [(False, 0), (True, 0), (True, 1)])
+@pytest.mark.parametrize("compact,splat_kernel", [(False, 2), (True, 0), (True, 1), (True, 2)])
 def test_gpu_radial_kernel_random_particles(compact, splat_kernel):
     """The radial kernel W(|d|) through the test hook: hand-placed boundary
     and ring particles of every bucket (small footprints one point per lane,
@@ -438,21 +438,24 @@ def test_gpu_radial_kernel_random_particles(compact, splat_kernel):
     assert e <= 1e-5
 
 
-@pytest.mark.parametrize("name,steps,kernel", [("c2", 60, 0), ("p0", 40, 0), ("c3", 12, 0), ("c2", 60, 1),
-                                               ("p0", 40, 1)])
-def test_quadrant_schedule_scenes(name, steps, kernel):
-    """The quadrant-per-wavefront splat schedule in the batched form (both
-    crest/trough kernels): integer state bit-exact and heights against the
-    oracle, as for the default schedule."""
+@pytest.mark.parametrize("name,steps,kernel,schedule", [("c2", 60, 0, 0), ("p0", 40, 0, 0), ("c3", 12, 0, 0),
+                                                        ("c5", 6, 0, 0), ("c2", 60, 1, 0), ("c2", 60, 0, 1),
+                                                        ("p0", 40, 0, 1), ("c3", 12, 0, 1), ("c2", 60, 1, 1),
+                                                        ("p0", 40, 1, 1)])
+def test_other_schedule_scenes(name, steps, kernel, schedule):
+    """The batch-per-wavefront splat schedule (0) and the quadrant-per-
+    wavefront one (1) in the batched form (both crest/trough kernels):
+    integer state bit-exact and heights against the oracle, as for the
+    default hybrid schedule (2) that every other test runs."""
     s = scenes.get(name).replace(kernel=kernel)
-    say(f"quadrant schedule {name} kernel={kernel} {steps} steps")
+    say(f"schedule {schedule} {name} kernel={kernel} {steps} steps")
     g, o = make(s, compact=True, batched=True)
-    use_schedule(g, 1)
+    use_schedule(g, schedule)
     g.step(steps)
     o.step(steps)
     check_integer_state(g, o, s)
     e = check_heights(g, o, s, patches=[0, 1, len(s.patches) - 1] if len(s.patches) > 3 else None)
-    say(f"quadrant schedule {name} kernel={kernel} err={e}")
+    say(f"schedule {schedule} {name} kernel={kernel} err={e}")
 
 
 @pytest.mark.parametrize("name,steps,form", [("c1", 30, "plain"), ("c2", 60, "batched"),
