@@ -132,22 +132,26 @@ DOM_KERNEL = {"splat": "k_splat<RecCompact, false, false>", "fft_a": "k_fft_a", 
               "deposit_x": "k_deposit_x<RecCompact>", "filter_y": "k_filter_y", "layer_sum": "k_layer_sum"}
 
 
-def measured_traffic(config, dom, radial=False, splat_kernel=2):
+def measured_traffic(config, dom, radial=False, tuned=None, bins=None):
     """HBM bytes per launch of the dominant kernel from profiles/traffic.json
     (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
     reads for a device copy of known size), or None when there is no entry
-    for this workload and kernel or the kernel sources changed since."""
+    for this workload, kernel, bin edges and splat partition, or the kernel
+    sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     e = json.load(open(path)).get(config)
+    splat_kernel = tuned["plan"].get("splat_kernel", 2) if tuned else 2
     name = DOM_KERNEL.get(dom)
     if dom == "splat":   # the schedule and the crest/trough kernel are template instances
         name = ("k_splat", "k_splat_q", "k_splat_h")[splat_kernel] + \
             ("<RecCompact, true, false>" if radial else "<RecCompact, false, false>")
     if not e or e.get("kernel") != name:
         return None
+    if e.get("plan") != (tuned["plan"] if tuned else None) or e.get("bins") != bins:
+        return None   # measured with other bin edges or another partition
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in e["sources"])).hexdigest()
     return int(e["bytes_per_launch"]) if h == e["sources_sha256"] else None
 
@@ -385,7 +389,7 @@ def main():
     scene_p = scene
     if not args.no_tune and not layers:
         from paper_2511_02852_amd import autotune
-        tuned = autotune.tune(scene, preroll, log=log)
+        tuned = autotune.tune(scene, preroll, cache=autotune.TUNED_PATH, log=log)
         scene_p = scene.replace(bins=tuned["bins"])
         log(f"[bench] autotuned: bins {tuned['bins']}, plan {tuned['plan']} "
             f"({tuned['frame_ms']:.4f} vs default {tuned['default_frame_ms']:.4f} ms/frame in the search)")
@@ -494,7 +498,7 @@ def main():
     t_hbm = alg[dom] / (HBM_PEAK_GBS * 1e9)
     t_mfma = flops_dom / (FP32_PEAK_TFLOPS * 1e12)
     traffic = measured_traffic(args.config + ("-layers" if layers else "") + ("-radial" if radial else ""), dom,
-                               radial, tuned["plan"].get("splat_kernel", 2) if tuned else 2)
+                               radial, tuned, tuned["bins"] if tuned else None)
     if (layers or radial) and t_mfma > t_hbm:
         # the layer passes and the radial kernel are FP32 vector work (no
         # matrix cores): bound by the vector ALUs, FP32 vector peak 157.3 TFLOP/s

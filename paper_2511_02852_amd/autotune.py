@@ -45,9 +45,13 @@ def scene_signature(scene) -> str:
 
 
 def device_name() -> str:
+    """Architecture and compute-unit count of the current device (the
+    marketing name and the target-feature suffix of the architecture can
+    differ between runtimes on the same part)."""
     import torch
     p = torch.cuda.get_device_properties(torch.cuda.current_device())
-    return f"{p.name}|{getattr(p, 'gcnArchName', '')}|{p.multi_processor_count}"
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return f"{arch.split(':')[0]}|{p.multi_processor_count}"
 
 
 def bins_fit(edge: int, r_cells: float) -> bool:
@@ -86,6 +90,13 @@ def default_cache_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "hwo_autotune.json")
 
 
+# Settings tuned on the target device for the benchmark scenes, shipped with
+# the package so that timed runs and their hardware-counter profiles use the
+# same bin edges and partition (the search itself varies by a few percent
+# from run to run); a scene or device without an entry is tuned and added.
+TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
+
+
 def _time_frames(ocean, frames: int) -> float:
     import torch
     torch.cuda.synchronize()
@@ -110,9 +121,9 @@ def tune(scene, preroll: int, cache: Optional[str] = None, reps: int = 8, frames
          search_bins: bool = True, log: Callable[[str], None] = lambda s: None, margin: float = 0.02) -> dict:
     """Bin edges and splat partition for the production form of a scene
     (16-byte records, batched launches, graph replay), from the cache when
-    present.  Another set of bin edges replaces the scene's only when its
-    frames are faster by more than `margin` (timing noise of a few tens of
-    frames is about that size).  Returns {"bins", "plan", "frame_ms",
+    present.  Another set of bin edges, or the partition the library's search
+    finds, replaces the scene's own only when its frames are faster by more
+    than `margin` (timing noise of a few tens of frames is about that size).  Returns {"bins", "plan", "frame_ms",
     "default_frame_ms", "candidates", "cached"}."""
     from . import hwo
     path = cache or default_cache_path()
@@ -135,14 +146,16 @@ def tune(scene, preroll: int, cache: Optional[str] = None, reps: int = 8, frames
         _spin(g, preroll)
         # frames with the starting partition, then with the searched one: the
         # search times the splat alone, so its pick is kept only when whole
-        # frames are faster with it too
+        # frames are faster with it by more than the margin too (a partition
+        # with more parts writes more partial tiles, so a tie keeps the
+        # starting one)
         plan0 = g.get_plan()
         ms0 = _time_frames(g, frames)
         if bins == base:
             default_ms = ms0
         plan, best, start = g.autotune(reps)
         ms = _time_frames(g, frames)
-        if ms >= ms0:
+        if ms >= ms0 * (1.0 - margin):
             plan, ms = plan0, ms0
         g.close()
         results.append({"bins": bins, "plan": plan, "frame_ms": ms, "splat_ms": best, "splat_ms_start": start})
