@@ -181,9 +181,12 @@ int hwo_set_spectrum(hwo_ocean *o, const hwo_spectrum *sp);
  * object where the particle field replaces the FFT (Sec 3.1 local
  * replacement; boundary injection Sec 3.3, Eq 18).  Max 127 patches; *id
  * receives its index (dense, in call order; it selects the patch's RNG
- * streams).  HWO_EINVAL for a bad size or dx, and, with dir_mode 1, for an
+ * streams).  HWO_EINVAL for a bad size or dx (the larger side times dx
+ * at most 1.5e9 position units of 2^-20 m), and, with dir_mode 1, for an
  * effective eta that is not a whole number in 1..10368 (one direction code
- * per particle at most); HWO_ESTATE after the first step. */
+ * per particle at most); HWO_ESTATE after the first step.  The first step
+ * also fails with HWO_EINVAL when the larger side plus a bucket's survival
+ * margin (2 r) reaches 2^31 position units. */
 int hwo_add_patch(hwo_ocean *o, const hwo_patch *p, int32_t *id);
 /* Add a moving object that disturbs the water (Sec 4.3, object acts on
  * water): a disc emitting rings of particles into patch src->patch, into the

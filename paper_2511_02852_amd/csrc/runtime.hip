@@ -533,6 +533,11 @@ static int build_scene_tables(hwo_ocean *o) {
       // computation", 2019); binu >= 2 here
       P.binm[i] = UINT64_MAX / (uint64_t)binu + 1;
       const int64_t m = o->margin[i];
+      // a live particle lies within the window plus the margin, so its offset
+      // from any cell of the patch is below nx dxu + m, which the splat forms
+      // in 32 bits
+      if ((int64_t)std::max(hp.nx, hp.ny) * P.dxu + m >= ((int64_t)1 << 31))
+        return o->fail(HWO_EINVAL, "patch plus the bucket's survival margin exceed 2^31 position units");
       P.nbx[i] = (int32_t)(floor_div((int64_t)hp.nx * P.dxu + 2 * m, binu) + 1);
       P.nby[i] = (int32_t)(floor_div((int64_t)hp.ny * P.dxu + 2 * m, binu) + 1);
       P.binbase[i] = (int32_t)bins;

@@ -480,14 +480,26 @@ __device__ __forceinline__ DecIn dec_load(const Dev &d, const Rec &r, int64_t n,
 }
 
 // Crest (cx, cy) in tile cells and signed amplitude A (0: nothing to splat);
-// the trough lies rc u behind the crest.
+// the trough lies rc u behind the crest.  The offset of a particle of the
+// sorted buffer from the tile's first cell centre is less than 2^31 position
+// units (the library rejects windows plus survival margins of 2^31 units or
+// more), so it is formed modulo 2^32 from the low words, which is exact and
+// needs one conversion instruction; caller-supplied records (`wide`) can lie
+// anywhere and take the 64-bit path.
 template <class Rec>
 __device__ __forceinline__ void dec_point(const Dev &d, int64_t n, const DecIn &i, const TileGeom &T, float Ab,
-                                          float &cx, float &cy, float &A) {
-  const int64_t px = (int64_t)i.ox + (((int64_t)i.age * i.v.x) >> 12);
-  const int64_t py = (int64_t)i.oy + (((int64_t)i.age * i.v.y) >> 12);
-  cx = (float)(px - T.X0) * T.inv_dxu;
-  cy = (float)(py - T.Y0) * T.inv_dxu;
+                                          float &cx, float &cy, float &A, bool wide) {
+  if (wide) {
+    const int64_t px = (int64_t)i.ox + (((int64_t)i.age * i.v.x) >> 12);
+    const int64_t py = (int64_t)i.oy + (((int64_t)i.age * i.v.y) >> 12);
+    cx = (float)(px - T.X0) * T.inv_dxu;
+    cy = (float)(py - T.Y0) * T.inv_dxu;
+  } else {
+    const uint32_t mx = (uint32_t)(((int64_t)i.age * i.v.x) >> 12);
+    const uint32_t my = (uint32_t)(((int64_t)i.age * i.v.y) >> 12);
+    cx = (float)(int32_t)((uint32_t)i.ox + mx - (uint32_t)T.X0) * T.inv_dxu;
+    cy = (float)(int32_t)((uint32_t)i.oy + my - (uint32_t)T.Y0) * T.inv_dxu;
+  }
   const uint32_t lv = (i.flags >> 2) & 7u;
   const float inv3 = lv == 0 ? 1.f : lv == 1 ? 1.f / 3.f : lv == 2 ? 1.f / 9.f : lv == 3 ? 1.f / 27.f : 1.f / 81.f;
   if (!(i.flags & 1u)) A = 0.f;
@@ -707,7 +719,7 @@ __global__ __launch_bounds__(kThreads, 3) void k_splat(Dev d, int t0, int nt, co
       // ---- this batch's points: a crest and a trough per lane
       const int b = b0;
       float cx, cy, A;
-      dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A);
+      dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A, direct != nullptr);
       const float rc = d.bucket_r[b] / (float)P.dx;   // radius in cells
       const float qs = 0.25f / rc;                    // revolutions of the cosine per cell
       const int span = (int)floorf(2.f * rc) + 1;    // cells per axis a footprint reaches
@@ -1031,7 +1043,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_q(Dev d, int t0, int nt, 
         const int b = rec_b;
         const DecIn in = dec_load<Rec>(d, rec, n, b, T.p, true);
         float cx, cy, A;
-        dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A);
+        dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A, direct != nullptr);
         const float rc = d.bucket_r[b] / (float)P.dx;
         const float rev = (float)in.code * (1.0f / (float)kNCode);
         const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
@@ -1357,7 +1369,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
         }
         const int b = b0;
         float cx, cy, A;
-        dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A);
+        dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A, direct != nullptr);
         const float rc = d.bucket_r[b] / (float)P.dx;
         const float qs = 0.25f / rc;
         const float rev = (float)in0.code * (1.0f / (float)kNCode);
@@ -1422,7 +1434,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
           const int b = rec_b;
           const DecIn in = dec_load<Rec>(d, rec, n, b, T.p, true);
           float cx, cy, A;
-          dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A);
+          dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A, direct != nullptr);
           const float rc = d.bucket_r[b] / (float)P.dx;
           const float rev = (float)in.code * (1.0f / (float)kNCode);
           const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
