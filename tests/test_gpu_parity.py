@@ -649,6 +649,26 @@ def test_capacity_overflow_reported():
     check_integer_state(g1, o1, s)
 
 
+def test_patch_plus_margin_beyond_32_bit_offsets_rejected():
+    """The splat forms a particle's offset from its tile in 32 bits, which is
+    exact while a patch side plus a bucket's survival margin stays below 2^31
+    position units; a scene beyond that (a 1280 m patch with 700-900 m waves)
+    is rejected at its first step, and a slightly smaller patch is not."""
+    from paper_2511_02852_amd import hwo
+    sp = scenes.Spectrum(U10=15.0, n_buckets=1, lambda_min=700.0, lambda_max=900.0)
+    big = scenes.Scene(name="wide", fft_n=16, fft_L=4096.0, dt=0.01, spectrum=sp,
+                       patches=[scenes.Patch(anchor_x=0.0, anchor_y=0.0, nx=4096, ny=64, dx=0.3125)],
+                       bins=[2048])
+    with pytest.raises(hwo.HwoError) as ei:
+        g = hwo.Ocean(big)
+        g.step(1)
+    assert ei.value.code == hwo.HWO_EINVAL
+    ok = big.replace(patches=[scenes.Patch(anchor_x=0.0, anchor_y=0.0, nx=3072, ny=64, dx=0.3125)])
+    g = hwo.Ocean(ok)
+    g.step(1)
+    g.close()
+
+
 def test_empty_scene_and_zero_steps():
     from paper_2511_02852_amd import hwo
     s = scenes.Scene(name="empty", fft_n=32, fft_L=100.0, seed=1, spectrum=scenes.Spectrum(n_buckets=2))
