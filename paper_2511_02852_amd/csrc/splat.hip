@@ -40,6 +40,10 @@
 //     every lane computes the one row weight and the one column weight it
 //     supplies.  The four accumulators of every wavefront are added to the
 //     LDS tile at the end of the item.
+// Two more schedules of the same items follow k_splat: k_splat_q (the block
+// decodes records into LDS and each wavefront owns one quadrant) and
+// k_splat_h, the default, which runs each item's small-footprint buckets as
+// k_splat does and then its large-footprint buckets as k_splat_q does.
 // A tile with one part is blended and written straight from LDS.  Parts of a
 // split tile store their partial tile; k_splat_reduce (the next launch, so
 // every store is visible on every XCD) sums them and runs the blend.
