@@ -320,11 +320,13 @@ __global__ __launch_bounds__(kThreads) void k_fft_a(Dev d) {
 }
 
 template <int N> struct FftShapeB {
-  // row pairs per block; large transforms take 64 KiB of rows so that each
-  // half-plane row is read in runs of at least 32 bytes
+  // row pairs per block; 4096-point transforms take 64 KiB of rows so that
+  // each half-plane row is read in runs of at least 32 bytes; 2048-point
+  // ones take two row pairs (runs of 32 bytes, two blocks per CU: 12.0 us
+  // per pass against 12.4 us with four pairs in 512-thread blocks)
   static constexpr int F0 = FftShape<N>::F < N / 2 ? FftShape<N>::F : N / 2;
-  static constexpr int F = (N >= 2048) ? 65536 / (8 * N) : F0;
-  static constexpr int B = (N == 2048) ? 2 * kThreads : kThreads;   // threads per block (measured best)
+  static constexpr int F = (N == 2048) ? 2 : (N >= 4096) ? 65536 / (8 * N) : F0;
+  static constexpr int B = kThreads;   // threads per block
   static constexpr int T = B / F;
 };
 
