@@ -89,22 +89,50 @@ __device__ __forceinline__ uint32_t visit_cost(float rc) {
 // One wavefront per output tile: estimated splat cost of the tile, the
 // particles its work items will visit (the bins within 2 r of the tile, per
 // bucket, read from the bin offsets of this step) weighted by visit cost.
+constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
+
+// The loads go out in two rounds: lane b reads bucket b's bin rectangle and
+// tables, then every (bucket, row) pair of the tile reads its two offsets,
+// all before any is used.
 __global__ __launch_bounds__(kThreads) void k_splat_load(Dev d, int t0, int nt) {
   const int t = (int)blockIdx.x * (kThreads / 64) + ((int)threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= nt) return;
   const int tile = t0 + t;
   const PatchDev &P = d.patches[d.tile_patch[tile]];
-  uint64_t load = 0;
-  for (int b = 0; b < d.nb; ++b) {
-    const short4 rc = d.tile_rect[(size_t)tile * d.nb + b];
-    uint32_t seen = 0;
-    if (lane < rc.w) {
-      const int rb = P.binbase[b] + (rc.z + lane) * P.nbx[b];
-      seen = (uint32_t)max(0, min(d.off[rb + rc.y + 1], d.cap) - min(d.off[rb + rc.x], d.cap));
-    }
-    load += (uint64_t)seen * visit_cost(d.bucket_r[b] / (float)P.dx);
+  const int nb = d.nb;
+  int rxy = 0, rzw = 0, base = 0, nbx = 0;
+  uint32_t cost = 0;
+  if (lane < nb) {
+    const short4 rc = d.tile_rect[(size_t)tile * nb + lane];
+    rxy = (int)(uint16_t)rc.x | ((int)(uint16_t)rc.y << 16);
+    rzw = (int)(uint16_t)rc.z | ((int)(uint16_t)rc.w << 16);
+    base = P.binbase[lane];
+    nbx = P.nbx[lane];
+    cost = visit_cost(d.bucket_r[lane] / (float)P.dx);
   }
+  constexpr int kPer = kMaxBuckets * kMaxRows / 64;   // (bucket, row) pairs per lane
+  int lo[kPer], hi[kPer];
+  uint32_t cw[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int q = lane + 64 * k;
+    const int b = q / kMaxRows, r = q % kMaxRows;
+    const int xy = __shfl(rxy, b & 63), zw = __shfl(rzw, b & 63);
+    const int bb = __shfl(base, b & 63), bn = __shfl(nbx, b & 63);
+    cw[k] = (uint32_t)__shfl((int)cost, b & 63);
+    lo[k] = 0;
+    hi[k] = 0;
+    if (b < nb && r < (int)((uint32_t)zw >> 16)) {
+      const int rb = bb + ((zw & 0xFFFF) + r) * bn;
+      lo[k] = d.off[rb + (xy & 0xFFFF)];
+      hi[k] = d.off[rb + (int)((uint32_t)xy >> 16) + 1];
+    }
+  }
+  uint64_t load = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    load += (uint64_t)(uint32_t)max(0, min(hi[k], d.cap) - min(lo[k], d.cap)) * cw[k];
   for (int o = 32; o > 0; o >>= 1) load += __shfl_xor(load, o);
   if (lane == 0) d.tile_load[tile] = (uint32_t)min<uint64_t>(load, 0xFFFFFFFFull);
 }
@@ -348,7 +376,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(Dev d, int nbins, int
 }
 
 // ---------------------------------------------------------------- splat
-constexpr int kMaxRows = 32;       // bin rows a tile can need per bucket
 constexpr int kSplit = 8;          // records per aligned block when a tile's lists are dealt to its parts
 
 // Entries of part j of np among the record indices [0, x): those in the
