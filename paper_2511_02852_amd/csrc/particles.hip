@@ -558,8 +558,16 @@ int scan_blocks(int nbins) { return (nbins + kScanChunk - 1) / kScanChunk; }
 __global__ __launch_bounds__(kThreads) void k_scan_a(Dev d, int lo, int hi) {
   __shared__ int32_t s[kThreads];
   const int beg = lo + blockIdx.x * kScanChunk;
+  const int end = min(hi, beg + kScanChunk);
+  int32_t v[kScanPer];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {   // all loads before the sum
+    const int i = beg + (int)threadIdx.x + k * kThreads;
+    v[k] = i < end ? d.hist[i] : 0;
+  }
   int32_t sum = 0;
-  for (int i = beg + threadIdx.x; i < min(hi, beg + kScanChunk); i += kThreads) sum += d.hist[i];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) sum += v[k];
   s[threadIdx.x] = sum;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
