@@ -391,9 +391,19 @@ __device__ __forceinline__ int part_entry(int k, int j, int np) {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
+// Largest of v (clamped to 0..F) over the wavefront's lanes: a wave-uniform
+// loop bound held in a scalar register.
+template <int F>
+__device__ __forceinline__ int wave_max_upto(int v) {
+  int m = 0;
+#pragma unroll
+  for (int u = 1; u <= F; ++u) m += __ballot(v >= u) != 0ull;
+  return m;
+}
+
 // Small footprints (at most F cells per axis): one crest or trough per lane,
-// weights in registers, LDS float atomics into the tile.  Loops stop as soon
-// as no lane of the wavefront has work left in them.
+// weights in registers, LDS float atomics into the tile.  The loops run to
+// the wavefront's largest column and row counts, found once per point.
 template <int F>
 __device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv, bool valid, float rc, float qs,
                                              int tw, int th) {
@@ -404,6 +414,7 @@ __device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv
     nc = min(F, min(tw - 1, (int)floorf(pv.x + rc)) - ilo + 1);
     nr = min(F, min(th - 1, (int)floorf(pv.y + rc)) - jlo + 1);
   }
+  const int ncw = wave_max_upto<F>(nc), nrw = wave_max_upto<F>(nr);
   // offsets of the first column and row from the centre (cells), then
   // q = offset / (4 r) per cell
   const float dx0 = (float)ilo - pv.x, dy0 = (float)jlo - pv.y;
@@ -411,17 +422,18 @@ __device__ __forceinline__ void splat_points(float (*acc)[kPad], const float4 pv
 #pragma unroll
   for (int u = 0; u < F; ++u) {
     wx[u] = 0.f;
-    if (__any(u < nc)) wx[u] = pv.z * wrev((dx0 + (float)u) * qs);
+    if (u < ncw) wx[u] = pv.z * wrev((dx0 + (float)u) * qs);
   }
 #pragma unroll
   for (int jj = 0; jj < F; ++jj) {
-    if (!__any(jj < nr)) break;
+    if (jj >= nrw) break;
     const float wy = wrev((dy0 + (float)jj) * qs);
     float *row = &acc[min(jlo + jj, kTile - 1)][ilo];
+    const bool rok = jj < nr;
 #pragma unroll
     for (int ii = 0; ii < F; ++ii) {
-      if (!__any(ii < nc)) break;
-      if (jj < nr && ii < nc) atomicAdd(row + ii, wy * wx[ii]);
+      if (ii >= ncw) break;
+      if (rok && ii < nc) atomicAdd(row + ii, wy * wx[ii]);
     }
   }
 }
@@ -438,18 +450,20 @@ __device__ __forceinline__ void splat_points_radial(float (*acc)[kPad], const fl
     nc = min(F, min(tw - 1, (int)floorf(pv.x + rc)) - ilo + 1);
     nr = min(F, min(th - 1, (int)floorf(pv.y + rc)) - jlo + 1);
   }
+  const int ncw = wave_max_upto<F>(nc), nrw = wave_max_upto<F>(nr);
   const float dx0 = (float)ilo - pv.x, dy0 = (float)jlo - pv.y;
 #pragma unroll
   for (int jj = 0; jj < F; ++jj) {
-    if (!__any(jj < nr)) break;
+    if (jj >= nrw) break;
     const float dy = dy0 + (float)jj;
     float *row = &acc[min(jlo + jj, kTile - 1)][ilo];
+    const bool rok = jj < nr;
 #pragma unroll
     for (int ii = 0; ii < F; ++ii) {
-      if (!__any(ii < nc)) break;
+      if (ii >= ncw) break;
       const float dx = dx0 + (float)ii;
       const float w = wrev(__builtin_amdgcn_sqrtf(dx * dx + dy * dy) * qs);
-      if (jj < nr && ii < nc && w != 0.f) atomicAdd(row + ii, pv.z * w);
+      if (rok && ii < nc && w != 0.f) atomicAdd(row + ii, pv.z * w);
     }
   }
 }
@@ -1242,6 +1256,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
   __shared__ int s_cnt[kMaxBuckets];          // entries of this part in each bucket's list
   __shared__ int s_bat[kMaxBuckets + 1];      // phase 1: first batch of the j-th bucket taken (bucket nb - 1 - j)
   __shared__ int s_boff[kMaxBuckets + 1];     // phase 2: offsets of the large buckets in the item's list
+  __shared__ float2 s_rq[kMaxBuckets];         // radius in cells, revolutions of the cosine per cell
   __shared__ int s_tile, s_part, s_nparts, s_patch;
   __shared__ unsigned long long s_prof[kProf ? PROF_N : 1];
 
@@ -1324,6 +1339,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
       // bucket j for the phase-2 offsets
       int cnt1 = 0, cnt2 = 0;
       if (lane < nb) {
+        const float rcl = d.bucket_r[lane] / (float)P.dx;
+        s_rq[lane] = make_float2(rcl, 0.25f / rcl);
         const int b = nb - 1 - lane;
         const int span = (int)floorf(2.f * d.bucket_r[b] / (float)P.dx) + 1;
         const int cnt = s_pre[b][s_nrows[b]];
@@ -1401,8 +1418,9 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
         const int b = b0;
         float cx, cy, A;
         dec_point<Rec>(d, n, in0, T, P.A[b], cx, cy, A, direct != nullptr);
-        const float rc = d.bucket_r[b] / (float)P.dx;
-        const float qs = 0.25f / rc;
+        const float2 rq = s_rq[b];
+        const float rc = rq.x, qs = rq.y;
+        const int span = (int)floorf(2.f * rc) + 1;
         const float rev = (float)in0.code * (1.0f / (float)kNCode);
         const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
         const DecIn in1 = dec_load<Rec>(d, r1, n, b1, T.p, k1 < nbat && lane < c1);
@@ -1411,14 +1429,18 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
         mark(PROF_DECODE);
         const float4 pc = make_float4(cx, cy, A, 0.f), ptr = make_float4(tx, ty, -A, 0.f);
         const bool live = A != 0.f;
+        // loops sized to the bucket's span (wave-uniform)
         if constexpr (kRadial) {
-          if ((int)floorf(2.f * rc) + 1 <= 4) {   // wave-uniform
+          if (span <= 4) {
             splat_points_radial<4>(acc, pc, live, rc, qs, T.tw, T.th);
             splat_points_radial<4>(acc, ptr, live, rc, qs, T.tw, T.th);
           } else {
             splat_points_radial<8>(acc, pc, live, rc, qs, T.tw, T.th);
             splat_points_radial<8>(acc, ptr, live, rc, qs, T.tw, T.th);
           }
+        } else if (span <= 2) {
+          splat_points<2>(acc, pc, live, rc, qs, T.tw, T.th);
+          splat_points<2>(acc, ptr, live, rc, qs, T.tw, T.th);
         } else {
           splat_points<kAtomicSpan>(acc, pc, live, rc, qs, T.tw, T.th);
           splat_points<kAtomicSpan>(acc, ptr, live, rc, qs, T.tw, T.th);
@@ -1466,7 +1488,7 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
           const DecIn in = dec_load<Rec>(d, rec, n, b, T.p, true);
           float cx, cy, A;
           dec_point<Rec>(d, n, in, T, P.A[b], cx, cy, A, direct != nullptr);
-          const float rc = d.bucket_r[b] / (float)P.dx;
+          const float rc = s_rq[b].x;
           const float rev = (float)in.code * (1.0f / (float)kNCode);
           const float tx = cx - rc * __builtin_amdgcn_cosf(rev), ty = cy - rc * __builtin_amdgcn_sinf(rev);
           auto quads = [&](float x, float y) {
@@ -1485,8 +1507,8 @@ __global__ __launch_bounds__(kThreads, 5) void k_splat_h(Dev d, int t0, int nt, 
           if (seg_hi <= seg_lo) continue;   // block-uniform
           if constexpr (kProf)
             if (tid == 0) atomicAdd(&s_prof[PROF_POINTS + b], (unsigned long long)(2 * (seg_hi - seg_lo)));
-          const float rc = d.bucket_r[b] / (float)P.dx;
-          const float qs = 0.25f / rc;
+          const float2 rq = s_rq[b];
+          const float rc = rq.x, qs = rq.y;
           const int q_lo = 2 * seg_lo, q_hi = 2 * seg_hi;
           if (quad_live) {
             if constexpr (kRadial) {
