@@ -123,9 +123,16 @@ __global__ __launch_bounds__(kThreads) void k_windows(Dev d) {
 }
 
 // ---------------------------------------------------------------- k_params
+// The injection and emission counts and their scans stay in LDS; global
+// memory gets the scanned offsets once, and the counters are bumped with
+// atomics, so no step waits on a global read of what the block just wrote.
+constexpr int kParamsPer = 4;   // injection slots per thread whose rate loads are in flight together
+
 __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
   __shared__ int64_t s_n;
   __shared__ int32_t s_tmp[kThreads / 64];
+  __shared__ int32_t s_inj[kMaxInjSlots + 1];
+  __shared__ int32_t s_em[kMaxSources + 1];
   const int tid = threadIdx.x;
   if (tid == 0) {
     const int64_t n = d.glob->n + 1;
@@ -152,11 +159,23 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
 
   // injection counts per (patch, bucket, pair), in that order
   const int ns_inj = d.n_inj_slots;
-  for (int q = tid; q < ns_inj; q += kThreads) {
-    const int p = q / (2 * d.nb), i = (q / 2) % d.nb, pair = q & 1;
-    const PatchDev &P = d.patches[p];
-    const uint64_t R = pair ? P.Ry[i] : P.Rx[i];
-    d.inj_off[q] = (int32_t)(cum_count(R, n) - cum_count(R, n - 1));
+  for (int q0 = 0; q0 < ns_inj; q0 += kThreads * kParamsPer) {
+    uint64_t R[kParamsPer];
+#pragma unroll
+    for (int k = 0; k < kParamsPer; ++k) {
+      const int q = q0 + tid + k * kThreads;
+      R[k] = 0;
+      if (q < ns_inj) {
+        const int pp = q / (2 * d.nb), i = (q / 2) % d.nb;
+        const PatchDev &P = d.patches[pp];
+        R[k] = (q & 1) ? P.Ry[i] : P.Rx[i];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kParamsPer; ++k) {
+      const int q = q0 + tid + k * kThreads;
+      if (q < ns_inj) s_inj[q] = (int32_t)(cum_count(R[k], n) - cum_count(R[k], n - 1));
+    }
   }
   // ring emissions in patch-sorted source order
   for (int k = tid; k < d.ns; k += kThreads) {
@@ -165,41 +184,38 @@ __global__ __launch_bounds__(kThreads) void k_params(Dev d) {
     // the horizontal-motion ring, then the vertical-motion ring, each on its cadence
     const bool emit_h = S.E > 0 && ((n - 1) % S.E) == 0;
     const bool emit_v = S.Eh > 0 && ((n - 1) % S.Eh) == 0;
-    const bool emit = emit_h || emit_v;
-    d.em_off[k] = (emit_h ? S.ne : 0) + (emit_v ? S.ne : 0);
-    if (emit) {
+    const int ne = (emit_h ? S.ne : 0) + (emit_v ? S.ne : 0);
+    s_em[k] = ne;
+    if (ne) {
       const PatchDev &P = d.patches[S.patch];
       const double xs = S.x0 + S.vx * tn;
       const double ys = S.y0 + S.vy * tn;
       d.src_pos[s] = make_int2((int32_t)round_away((xs - P.ax) * 1048576.0),
                                (int32_t)round_away((ys - P.ay) * 1048576.0));
+      atomicAdd(&d.ctr[((size_t)S.patch * d.nb + S.bucket) * CNT_NUM + CNT_EMIT], (unsigned long long)ne);
     }
   }
   __syncthreads();
   // counters of created particles (before the scan overwrites the counts)
   for (int q = tid; q < d.np * d.nb; q += kThreads) {
-    const int c = d.inj_off[2 * q] + d.inj_off[2 * q + 1];
-    if (c) d.ctr[(size_t)q * CNT_NUM + CNT_INJ] += (unsigned long long)c;
-  }
-  for (int k = tid; k < d.ns; k += kThreads) {
-    const int s = d.src_order[k];
-    const SourceDev &S = d.sources[s];
-    if (d.em_off[k])
-      atomicAdd(&d.ctr[((size_t)S.patch * d.nb + S.bucket) * CNT_NUM + CNT_EMIT], (unsigned long long)d.em_off[k]);
+    const int c = s_inj[2 * q] + s_inj[2 * q + 1];
+    if (c) atomicAdd(&d.ctr[(size_t)q * CNT_NUM + CNT_INJ], (unsigned long long)c);
   }
   __syncthreads();
-  const int32_t tot_inj = block_scan_excl(d.inj_off, ns_inj, s_tmp);
-  if (tid == 0) d.inj_off[ns_inj] = tot_inj;
-  const int32_t tot_em = block_scan_excl(d.em_off, d.ns, s_tmp);
-  if (tid == 0) d.em_off[d.ns] = tot_em;
+  const int32_t tot_inj = block_scan_excl(s_inj, ns_inj, s_tmp);
+  if (tid == 0) s_inj[ns_inj] = tot_inj;
+  const int32_t tot_em = block_scan_excl(s_em, d.ns, s_tmp);
+  if (tid == 0) s_em[d.ns] = tot_em;
   __syncthreads();
+  for (int q = tid; q <= ns_inj; q += kThreads) d.inj_off[q] = s_inj[q];
+  for (int k = tid; k <= d.ns; k += kThreads) d.em_off[k] = s_em[k];
   for (int p = tid; p < d.np; p += kThreads) {
     const PatchDev &P = d.patches[p];
     StepPatch &W = d.sp[p];
-    W.inj_lo = d.inj_off[p * 2 * d.nb];
-    W.inj_hi = d.inj_off[(p + 1) * 2 * d.nb];
-    W.em_lo = d.em_off[P.src_lo];
-    W.em_hi = d.em_off[P.src_hi];
+    W.inj_lo = s_inj[p * 2 * d.nb];
+    W.inj_hi = s_inj[(p + 1) * 2 * d.nb];
+    W.em_lo = s_em[P.src_lo];
+    W.em_hi = s_em[P.src_hi];
   }
 }
 
