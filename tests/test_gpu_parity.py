@@ -411,6 +411,20 @@ def test_gpu_splat_random_particles_subcell_radii(splat_kernel):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("synth,splat_kernel", [(0, 0), (0, 1), (0, 2), (1, 2)])
+def test_splat_of_no_records_is_zero(synth, splat_kernel):
+    """An empty record list splats to an all-zero map, in every splat
+    schedule and through the texel layers."""
+    from paper_2511_02852_amd import hwo
+    s = scenes.c2().replace(synth=synth)
+    g = hwo.Ocean(s, compact=True)
+    g.step(1)
+    use_schedule(g, splat_kernel)
+    h = g.test_splat(0, np.zeros((0, 10), dtype=np.int64))
+    assert h.shape == (s.patches[0].ny, s.patches[0].nx)
+    assert not np.any(h)
+
+
 @pytest.mark.parametrize("compact", [False, True])
 def test_gpu_texel_layers_random_particles(compact):
     """The texel-layer synthesis through the test hook: hand-placed boundary
