@@ -360,8 +360,8 @@ def main():
                     help="also run a plain device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build "
-              "(the multi-GPU sharding is a design note, not an implemented path).", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is described in the design notes, not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch
